@@ -1,0 +1,111 @@
+"""Seeded synthetic inputs.
+
+This module only draws random numbers; it holds none of the search method's
+arithmetic.  Both the GPU path's tests/benchmarks and the CPU oracle consume
+the arrays it returns, so the two sides see identical inputs.
+
+Recipe (numpy PCG64, float64 draws cast once to float32 with round to
+nearest even):
+
+* ``gaussian(n, d, seed)``: i.i.d. N(0, 1) rows.
+* ``Mixture(ncomp, d, seed)``: ``ncomp`` components with uniform weights,
+  centres mu_c ~ N(0, 4 I) (standard deviation 2) and per-component scale
+  sigma_c ~ U[0.5, 1.5]; a sample is mu_c + sigma_c * N(0, I), optionally
+  normalised to unit length in float64 before the cast.  The mixture
+  parameters are drawn once per seed and shared by database, query and
+  training draws, which use their own seeds.
+* ``uniform_rows(nrows, length, seed)``: U[0, 1) float32 rows (k-selection
+  benchmark input).
+* Large draws are split into chunks of ``CHUNK`` rows, chunk i seeded by
+  ``SeedSequence(seed).spawn`` child i, so any chunk can be regenerated alone
+  and chunks are drawn on several threads.
+"""
+from __future__ import annotations
+
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+CHUNK = 1 << 20
+
+
+def _threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _chunked(n: int, d: int, seed: int, fill) -> np.ndarray:
+    out = np.empty((n, d), np.float32)
+    nchunks = (n + CHUNK - 1) // CHUNK
+    children = np.random.SeedSequence(seed).spawn(max(nchunks, 1))
+
+    def work(i):
+        lo = i * CHUNK
+        hi = min(n, lo + CHUNK)
+        rng = np.random.Generator(np.random.PCG64(children[i]))
+        fill(rng, out[lo:hi])
+
+    if nchunks <= 1:
+        for i in range(nchunks):
+            work(i)
+    else:
+        with ThreadPoolExecutor(_threads()) as ex:
+            list(ex.map(work, range(nchunks)))
+    return out
+
+
+def gaussian(n: int, d: int, seed: int) -> np.ndarray:
+    """n x d float32 rows drawn i.i.d. N(0, 1)."""
+    def fill(rng, dst):
+        dst[...] = rng.standard_normal(dst.shape, dtype=np.float64)
+    return _chunked(n, d, seed, fill)
+
+
+def uniform_rows(nrows: int, length: int, seed: int) -> np.ndarray:
+    """nrows x length float32 values drawn U[0, 1)."""
+    def fill(rng, dst):
+        dst[...] = rng.random(dst.shape, dtype=np.float64)
+    return _chunked(nrows, length, seed, fill)
+
+
+class Mixture:
+    """Gaussian mixture with uniform weights, centres N(0, 4I), scales U[0.5, 1.5]."""
+
+    def __init__(self, ncomp: int, d: int, seed: int):
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+        self.ncomp = ncomp
+        self.d = d
+        self.mu = 2.0 * rng.standard_normal((ncomp, d))
+        self.sigma = rng.uniform(0.5, 1.5, size=ncomp)
+
+    def sample(self, n: int, seed: int, unit_norm: bool = False) -> np.ndarray:
+        mu, sigma, ncomp = self.mu, self.sigma, self.ncomp
+
+        def fill(rng, dst):
+            comp = rng.integers(0, ncomp, size=dst.shape[0])
+            v = mu[comp] + sigma[comp, None] * rng.standard_normal(dst.shape, dtype=np.float64)
+            if unit_norm:
+                v /= np.linalg.norm(v, axis=1, keepdims=True)
+            dst[...] = v
+        return _chunked(n, self.d, seed, fill)
+
+
+def choose_rows(n: int, count: int, seed: int) -> np.ndarray:
+    """The first `count` entries of a seeded permutation of range(n): used for
+    Forgy k-means initialisation and for drawing training samples without
+    replacement."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    if count > n:
+        raise ValueError("cannot choose more rows than exist")
+    return rng.permutation(n)[:count].astype(np.int64)
+
+
+# Seeds of the five workloads (base + offset: +0 database, +1 queries,
+# +2 training-sample choice, +3 coarse k-means init, +4+m PQ init,
+# +20 learned-nprobe training queries, +21 network init, +22 arrivals).
+SEED = {"exact_small": 101, "exact_large": 102, "ivfpq": 103, "mixed": 104, "learned": 105}
+
+
+def pq_init_rows(n: int, M: int, seed: int) -> np.ndarray:
+    """[M, 256] Forgy rows for the M sub-quantizers (seed + m each)."""
+    return np.stack([choose_rows(n, 256, seed + m) for m in range(M)])
