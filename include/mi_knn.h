@@ -1,0 +1,218 @@
+/*
+ * mi_knn.h -- C ABI of the MI355X (gfx950) k-NN / IVFADC library.
+ *
+ * The operations follow "Billion-scale similarity search with GPUs"
+ * (Johnson, Douze, Jegou): exact k-nearest-neighbour search with fused
+ * k-selection (Sections 2 and 5.1) and IVFADC search over product-quantizer
+ * codes (Sections 2, 5.2 and 5.3).
+ *
+ * Conventions for every call
+ *   - Array arguments are DEVICE pointers unless the comment says "host".
+ *     Matrices are dense, row-major, contiguous.  The caller owns all
+ *     argument memory; the library never frees it.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
+ *     enqueue their kernels on it and return; outputs are valid once the
+ *     stream has been synchronised.  Calls that must read a device value on
+ *     the host (training, adding) synchronise the stream and say so.
+ *   - Results of k-selections: row r holds the k best entries sorted best
+ *     first -- squared L2 ascending, inner product descending -- with ties
+ *     broken by the lower index.  If fewer than k candidates exist the tail
+ *     is padded with distance +inf (L2) or -inf (inner product) and index -1.
+ *   - The return value is a status; on error the outputs are unspecified,
+ *     an index object is left as it was, and mk_last_error() describes the
+ *     failure.  No call throws across the ABI.
+ *   - k must satisfy 1 <= k <= 1024 (the register-resident selector holds at
+ *     most 1024 entries, as WarpSelect in Section 4.2); larger k returns
+ *     MK_ERR_UNSUPPORTED.
+ *   - Scratch memory is taken from HIP's stream-ordered allocator and given
+ *     back on the same stream.
+ */
+#ifndef MI_KNN_H
+#define MI_KNN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MK_OK = 0,
+    MK_ERR_INVALID_ARG = -1,
+    MK_ERR_UNSUPPORTED = -2,
+    MK_ERR_OOM = -3,
+    MK_ERR_DEVICE = -4,
+    MK_ERR_STATE = -5
+} mk_status;
+
+/* Section 2: L2 is the main metric; "highest values" for inner products. */
+typedef enum { MK_METRIC_L2 = 0, MK_METRIC_IP = 1 } mk_metric;
+
+typedef void* mk_stream_t; /* a hipStream_t */
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char* mk_last_error(void);
+
+/* Library ABI version (major * 100 + minor). */
+int32_t mk_version(void);
+
+/*
+ * Squared L2 norms ||x_i||^2 of n rows of dimension d (Section 2, Eq. 2: the
+ * norm terms take one pass over the matrix).
+ *   x   [n, d] float32        out [n] float32
+ */
+mk_status mk_norms(const float* x, int64_t n, int32_t d, float* out, mk_stream_t stream);
+
+/*
+ * Row-wise k-selection (Section 2 problem statement; Section 4.2 WarpSelect,
+ * rebuilt for 64-lane wavefronts): for each row of a resident matrix return
+ * the k lowest values (largest = 0) or the k highest (largest != 0) with
+ * their column indices.
+ *   a    [nrows, len] float32 (finite values)
+ *   vals [nrows, k] float32   idx [nrows, k] int64
+ * len may be smaller than k (padded as above).  nrows = 0 is a no-op.
+ */
+mk_status mk_kselect(const float* a, int64_t nrows, int64_t len, int32_t k, int32_t largest,
+                     float* vals, int64_t* idx, mk_stream_t stream);
+
+/*
+ * Exact k-NN search (Section 2 Eq. 1-2; Section 5.1): distances of every
+ * query to every database row, with the q.y GEMM term computed by FP32 MFMA
+ * tiles whose outputs feed a register-resident k-selection in the same
+ * kernel, followed by a merge of database-chunk partial results.
+ *   xq [nq, d] float32, xb [nb, d] float32
+ *   D  [nq, k] float32 -- squared L2 (ascending) or inner product
+ *                         (descending), recomputed in the direct form
+ *                         sum_t (x_t - y_t)^2 (or sum_t x_t y_t) in FP32 for
+ *                         the returned rows
+ *   I  [nq, k] int64
+ * The selection keeps extra candidates beyond k (up to the 1024-entry
+ * selector) and re-ranks them by the direct form, which removes the
+ * cancellation error of ||x||^2 + ||y||^2 - 2<x,y>.  nb must be < 2^31.
+ * Supported d: 1..512.
+ */
+mk_status mk_knn_search(const float* xq, int64_t nq, const float* xb, int64_t nb, int32_t d,
+                        int32_t k, mk_metric metric, float* D, int64_t* I, mk_stream_t stream);
+
+/*
+ * As mk_knn_search, with the database norms ||y_i||^2 supplied by the caller
+ * (e.g. from mk_norms on a resident database; ignored for MK_METRIC_IP and
+ * may then be NULL).  yn [nb] float32.
+ */
+mk_status mk_knn_search_prenorm(const float* xq, int64_t nq, const float* xb, const float* yn,
+                                int64_t nb, int32_t d, int32_t k, mk_metric metric, float* D,
+                                int64_t* I, mk_stream_t stream);
+
+/*
+ * k-means assignment step (Section 6.2: exact search with k = 1): for each
+ * point the nearest centroid (squared L2, ties to the lower index) and that
+ * squared distance (direct form, FP32).
+ *   x [n, d] float32, c [K, d] float32, assign [n] int64, dist [n] float32
+ *   (dist may be NULL).
+ */
+mk_status mk_kmeans_assign(const float* x, int64_t n, int32_t d, const float* c, int32_t K,
+                           int64_t* assign, float* dist, mk_stream_t stream);
+
+/*
+ * k-means update step (Section 2 "The quantizers": q1 is trained by k-means):
+ * each centroid becomes the mean of its points, accumulated in FP64 and
+ * rounded once to FP32.  Empty clusters are processed in increasing index
+ * order: the currently largest cluster b (ties to the lower index) is split,
+ * coordinate t of the empty centroid becoming c_b[t] * (1 + s_t 2^-10) and
+ * c_b[t] becoming c_b[t] * (1 - s_t 2^-10), s_t = +1 for even t and -1 for
+ * odd t (products in FP64, rounded to FP32); the empty cluster takes
+ * floor(count_b / 2) of b's count.
+ *   x [n, d], assign [n] int64 in [0, K), c [K, d] float32 in/out,
+ *   counts [K] int64 out (may be NULL).
+ * Synchronises the stream (the empty-cluster rule reads the counts on the
+ * host).
+ */
+mk_status mk_kmeans_update(const float* x, int64_t n, int32_t d, const int64_t* assign,
+                           int32_t K, float* c, int64_t* counts, mk_stream_t stream);
+
+/*
+ * Product-quantizer encoding (Section 2 "Product quantizer"): byte m of a
+ * vector's code is the nearest (squared L2, ties to the lower index) of the
+ * 256 centroids of sub-quantizer m over components [m d/M, (m+1) d/M).
+ *   r [n, d] float32, codebooks [M, 256, d/M] float32, codes [n, M] uint8
+ */
+mk_status mk_pq_encode(const float* r, int64_t n, int32_t d, int32_t M, const float* codebooks,
+                       uint8_t* codes, mk_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * IVFADC index (Section 2 Eq. 3-6; Section 5.2-5.3): coarse quantizer q1
+ * with nlist centroids, product quantizer q2 with M sub-quantizers of 256
+ * centroids (8-bit codes) on the residual y - q1(y), inverted lists holding
+ * codes and ids.  L2 only.  All index storage is resident in device memory
+ * and owned by the object.
+ * ------------------------------------------------------------------------ */
+typedef struct mk_ivfpq mk_ivfpq;
+
+/* d >= 1, nlist >= 1, M in {4, 8, ..., 64} with d % M == 0 (Section 5.2
+ * allows any multiple of 4 up to 64 sub-quantizers).  Allocates nothing on
+ * the device until training. */
+mk_status mk_ivfpq_create(int32_t d, int32_t nlist, int32_t M, mk_ivfpq** out);
+
+void mk_ivfpq_destroy(mk_ivfpq* index);
+
+/*
+ * Train q1 by k-means on xt (nt >= nlist rows, nt >= 256) then q2 by M
+ * independent 256-centroid k-means on the sub-vectors of the residuals of xt
+ * to the final coarse centroids, niter iterations each.  Initial centroids
+ * are rows of xt given by the caller (host arrays):
+ *   coarse_init_rows [nlist] int64, pq_init_rows [M, 256] int64.
+ * Also builds the query-independent term-1 table of Eq. 11.  Synchronises.
+ * Training again discards any added vectors.
+ */
+mk_status mk_ivfpq_train(mk_ivfpq* index, const float* xt, int64_t nt, int32_t niter,
+                         const int64_t* coarse_init_rows, const int64_t* pq_init_rows,
+                         mk_stream_t stream);
+
+/*
+ * Encode nb vectors and append them to their inverted lists with ids
+ * ntotal, ntotal+1, ... (entries of a list stay in id order).  Synchronises.
+ */
+mk_status mk_ivfpq_add(mk_ivfpq* index, const float* xb, int64_t nb, mk_stream_t stream);
+
+/* Number of vectors added so far. */
+int64_t mk_ivfpq_ntotal(const mk_ivfpq* index);
+
+/*
+ * IVFADC search (Algorithm 4 of Section 5.3): probe the nprobe nearest
+ * coarse centroids (Eq. 5), scan their lists with PQ lookup tables built
+ * from the three-term split of Eq. 11 and staged in LDS, select the k
+ * nearest of the scanned entries (Eq. 6).  D are ADC squared distances
+ * (FP32), I the ids.  1 <= nprobe <= min(nlist, 1024).
+ *   xq [nq, d] float32, D [nq, k] float32, I [nq, k] int64
+ */
+mk_status mk_ivfpq_search(mk_ivfpq* index, const float* xq, int64_t nq, int32_t k,
+                          int32_t nprobe, float* D, int64_t* I, mk_stream_t stream);
+
+/*
+ * Copy the trained quantizers to host arrays (any pointer may be NULL):
+ *   coarse [nlist, d] float32, codebooks [M, 256, d/M] float32.
+ * Synchronises.
+ */
+mk_status mk_ivfpq_get_quantizers(const mk_ivfpq* index, float* coarse, float* codebooks);
+
+/*
+ * Replace the quantizers with host arrays of the same shapes (as after
+ * training; the term-1 table is rebuilt and any added vectors are
+ * discarded).  Synchronises.
+ */
+mk_status mk_ivfpq_set_quantizers(mk_ivfpq* index, const float* coarse, const float* codebooks,
+                                  mk_stream_t stream);
+
+/*
+ * Copy the inverted lists to host arrays (any pointer may be NULL):
+ *   offsets [nlist + 1] int64 (CSR), codes [ntotal, M] uint8,
+ *   ids [ntotal] int64.  Synchronises.
+ */
+mk_status mk_ivfpq_get_lists(const mk_ivfpq* index, int64_t* offsets, uint8_t* codes,
+                             int64_t* ids);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MI_KNN_H */

@@ -1,0 +1,240 @@
+"""Thin Python binding of the C ABI declared in include/mi_knn.h.
+
+Every function here only checks and marshals arguments (torch tensors are
+used for device memory and the current HIP stream) and calls the library of
+the same name; all computation runs in the library's HIP kernels.  If the
+library has not been built, the first call raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmiknn.so")
+_lib = None
+
+MK_OK = 0
+_STATUS = {-1: "invalid argument", -2: "unsupported", -3: "out of memory", -4: "device error",
+           -5: "bad state"}
+METRICS = {"l2": 0, "ip": 1}
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_f32 = ctypes.c_float
+
+
+class MKError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn}: {_STATUS.get(status, status)} ({status}): {msg}")
+        self.status = status
+
+
+# name -> argtypes (restype int32 status unless listed in _RESTYPE)
+_SIGS = {
+    "mk_last_error": [],
+    "mk_version": [],
+    "mk_norms": [_vp, _i64, _i32, _vp, _vp],
+    "mk_kselect": [_vp, _i64, _i64, _i32, _i32, _vp, _vp, _vp],
+    "mk_knn_search": [_vp, _i64, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
+    "mk_knn_search_prenorm": [_vp, _i64, _vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
+    "mk_kmeans_assign": [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp],
+    "mk_kmeans_update": [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp],
+    "mk_pq_encode": [_vp, _i64, _i32, _i32, _vp, _vp, _vp],
+    "mk_ivfpq_create": [_i32, _i32, _i32, ctypes.POINTER(_vp)],
+    "mk_ivfpq_destroy": [_vp],
+    "mk_ivfpq_train": [_vp, _vp, _i64, _i32, _vp, _vp, _vp],
+    "mk_ivfpq_add": [_vp, _vp, _i64, _vp],
+    "mk_ivfpq_ntotal": [_vp],
+    "mk_ivfpq_search": [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp],
+    "mk_ivfpq_get_quantizers": [_vp, _vp, _vp],
+    "mk_ivfpq_set_quantizers": [_vp, _vp, _vp, _vp],
+    "mk_ivfpq_get_lists": [_vp, _vp, _vp, _vp],
+}
+_RESTYPE = {"mk_last_error": ctypes.c_char_p, "mk_ivfpq_destroy": None,
+            "mk_ivfpq_ntotal": ctypes.c_int64}
+
+
+def lib():
+    """Open the HIP library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1702_08734_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = _RESTYPE.get(name, ctypes.c_int32)
+    _lib = L
+    return L
+
+
+def _call(name: str, *args) -> None:
+    st = getattr(lib(), name)(*args)
+    if st != MK_OK:
+        msg = lib().mk_last_error()
+        raise MKError(name, st, msg.decode() if msg else "")
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None or t.numel() == 0 else t.data_ptr()
+
+
+def _out(shape, dtype, like: torch.Tensor) -> torch.Tensor:
+    return torch.empty(shape, dtype=dtype, device=like.device)
+
+
+def norms(x: torch.Tensor) -> torch.Tensor:
+    _dev(x, torch.float32, "x")
+    out = _out((x.shape[0],), torch.float32, x)
+    _call("mk_norms", _ptr(x), x.shape[0], x.shape[1], _ptr(out), _stream())
+    return out
+
+
+def kselect(a: torch.Tensor, k: int, largest: bool = False):
+    """Row-wise k smallest (or largest) values and their column indices."""
+    _dev(a, torch.float32, "a")
+    nrows, length = a.shape
+    vals = _out((nrows, k), torch.float32, a)
+    idx = _out((nrows, k), torch.int64, a)
+    _call("mk_kselect", _ptr(a), nrows, length, k, int(bool(largest)), _ptr(vals), _ptr(idx),
+          _stream())
+    return vals, idx
+
+
+def knn_search(xq: torch.Tensor, xb: torch.Tensor, k: int, metric: str = "l2",
+               yn: torch.Tensor | None = None):
+    """Exact k-NN: (D [nq, k] float32, I [nq, k] int64)."""
+    _dev(xq, torch.float32, "xq")
+    _dev(xb, torch.float32, "xb")
+    nq, d = xq.shape
+    nb = xb.shape[0]
+    if nb and xb.shape[1] != d:
+        raise ValueError("xq and xb dimensions differ")
+    D = _out((nq, k), torch.float32, xq)
+    I = _out((nq, k), torch.int64, xq)
+    if yn is None:
+        _call("mk_knn_search", _ptr(xq), nq, _ptr(xb), nb, d, k, METRICS[metric], _ptr(D),
+              _ptr(I), _stream())
+    else:
+        _dev(yn, torch.float32, "yn")
+        _call("mk_knn_search_prenorm", _ptr(xq), nq, _ptr(xb), _ptr(yn), nb, d, k,
+              METRICS[metric], _ptr(D), _ptr(I), _stream())
+    return D, I
+
+
+def kmeans_assign(x: torch.Tensor, c: torch.Tensor):
+    _dev(x, torch.float32, "x")
+    _dev(c, torch.float32, "c")
+    n, d = x.shape
+    a = _out((n,), torch.int64, x)
+    dist = _out((n,), torch.float32, x)
+    _call("mk_kmeans_assign", _ptr(x), n, d, _ptr(c), c.shape[0], _ptr(a), _ptr(dist), _stream())
+    return a, dist
+
+
+def kmeans_update(x: torch.Tensor, assign: torch.Tensor, c: torch.Tensor):
+    """Returns (new centroids, counts); c itself is left unchanged."""
+    _dev(x, torch.float32, "x")
+    _dev(assign, torch.int64, "assign")
+    _dev(c, torch.float32, "c")
+    n, d = x.shape
+    cn = c.clone()
+    counts = _out((c.shape[0],), torch.int64, x)
+    _call("mk_kmeans_update", _ptr(x), n, d, _ptr(assign), c.shape[0], _ptr(cn), _ptr(counts),
+          _stream())
+    return cn, counts
+
+
+def pq_encode(r: torch.Tensor, codebooks: torch.Tensor) -> torch.Tensor:
+    _dev(r, torch.float32, "r")
+    _dev(codebooks, torch.float32, "codebooks")
+    n, d = r.shape
+    M = codebooks.shape[0]
+    codes = _out((n, M), torch.uint8, r)
+    _call("mk_pq_encode", _ptr(r), n, d, M, _ptr(codebooks), _ptr(codes), _stream())
+    return codes
+
+
+class IVFPQ:
+    """Resident IVFADC index (coarse k-means + 8-bit PQ on residuals, L2)."""
+
+    def __init__(self, d: int, nlist: int, M: int):
+        self.d, self.nlist, self.M = d, nlist, M
+        h = _vp()
+        _call("mk_ivfpq_create", d, nlist, M, ctypes.byref(h))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.mk_ivfpq_destroy(h)
+            self._h = None
+
+    @property
+    def ntotal(self) -> int:
+        return int(lib().mk_ivfpq_ntotal(self._h))
+
+    def train(self, xt: torch.Tensor, niter: int, coarse_init_rows, pq_init_rows) -> None:
+        import numpy as np
+        _dev(xt, torch.float32, "xt")
+        ci = np.ascontiguousarray(coarse_init_rows, np.int64)
+        pi = np.ascontiguousarray(pq_init_rows, np.int64)
+        if ci.shape != (self.nlist,) or pi.shape != (self.M, 256):
+            raise ValueError("init rows must be [nlist] and [M, 256]")
+        _call("mk_ivfpq_train", self._h, _ptr(xt), xt.shape[0], niter, ci.ctypes.data,
+              pi.ctypes.data, _stream())
+
+    def add(self, xb: torch.Tensor) -> None:
+        _dev(xb, torch.float32, "xb")
+        _call("mk_ivfpq_add", self._h, _ptr(xb), xb.shape[0], _stream())
+
+    def search(self, xq: torch.Tensor, k: int, nprobe: int):
+        _dev(xq, torch.float32, "xq")
+        nq = xq.shape[0]
+        D = _out((nq, k), torch.float32, xq)
+        I = _out((nq, k), torch.int64, xq)
+        _call("mk_ivfpq_search", self._h, _ptr(xq), nq, k, nprobe, _ptr(D), _ptr(I), _stream())
+        return D, I
+
+    def get_quantizers(self):
+        import numpy as np
+        coarse = np.empty((self.nlist, self.d), np.float32)
+        books = np.empty((self.M, 256, self.d // self.M), np.float32)
+        _call("mk_ivfpq_get_quantizers", self._h, coarse.ctypes.data, books.ctypes.data)
+        return coarse, books
+
+    def set_quantizers(self, coarse, books) -> None:
+        import numpy as np
+        c = np.ascontiguousarray(coarse, np.float32)
+        b = np.ascontiguousarray(books, np.float32)
+        _call("mk_ivfpq_set_quantizers", self._h, c.ctypes.data, b.ctypes.data, _stream())
+
+    def get_lists(self):
+        import numpy as np
+        n = self.ntotal
+        offs = np.empty(self.nlist + 1, np.int64)
+        codes = np.empty((max(n, 1), self.M), np.uint8)
+        ids = np.empty(max(n, 1), np.int64)
+        _call("mk_ivfpq_get_lists", self._h, offs.ctypes.data, codes.ctypes.data, ids.ctypes.data)
+        return offs, codes[:n], ids[:n]

@@ -1,0 +1,75 @@
+// Shared host-side plumbing of the C ABI: status codes, the per-thread error
+// message, HIP error checks and stream-ordered scratch allocations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "mi_knn.h"
+
+namespace mk {
+
+void set_error(const std::string& msg);
+const char* get_error();
+
+#define MK_REQUIRE(cond, status, msg)                      \
+    do {                                                   \
+        if (!(cond)) {                                     \
+            ::mk::set_error(std::string(__func__) + ": " + (msg)); \
+            return (status);                               \
+        }                                                  \
+    } while (0)
+
+#define MK_HIP(expr)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            ::mk::set_error(std::string(__func__) + ": " #expr " failed: " +         \
+                            hipGetErrorString(e_));                                  \
+            return e_ == hipErrorOutOfMemory ? MK_ERR_OOM : MK_ERR_DEVICE;           \
+        }                                                                            \
+    } while (0)
+
+#define MK_LAUNCHED()                                                                \
+    do {                                                                             \
+        hipError_t e_ = hipGetLastError();                                           \
+        if (e_ != hipSuccess) {                                                      \
+            ::mk::set_error(std::string(__func__) + ": kernel launch failed: " +     \
+                            hipGetErrorString(e_));                                  \
+            return MK_ERR_DEVICE;                                                    \
+        }                                                                            \
+    } while (0)
+
+// Stream-ordered device scratch; freed on the same stream when it goes out of
+// scope, so a call never synchronises to release it.
+struct Scratch {
+    void* ptr = nullptr;
+    hipStream_t stream = nullptr;
+    Scratch() = default;
+    Scratch(const Scratch&) = delete;
+    Scratch& operator=(const Scratch&) = delete;
+    mk_status alloc(size_t bytes, hipStream_t s) {
+        stream = s;
+        if (bytes == 0) bytes = 256;
+        hipError_t e = hipMallocAsync(&ptr, bytes, s);
+        if (e != hipSuccess) {
+            ptr = nullptr;
+            set_error(std::string("scratch allocation of ") + std::to_string(bytes) +
+                      " bytes failed: " + hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? MK_ERR_OOM : MK_ERR_DEVICE;
+        }
+        return MK_OK;
+    }
+    template <class T>
+    T* as() const { return static_cast<T*>(ptr); }
+    ~Scratch() {
+        if (ptr) (void)hipFreeAsync(ptr, stream);
+    }
+};
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace mk

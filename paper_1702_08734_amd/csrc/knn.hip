@@ -1,0 +1,490 @@
+// Exact k-NN search (Section 2 Eq. 1-2, Section 5.1).
+//
+// Layout of one call:
+//   1. norms: ||y||^2 per database row (one pass, Eq. 2), skipped for inner
+//      products or when the caller supplies them;
+//   2. knn_tile_select: the grid is (query block) x (database chunk).  A
+//      workgroup keeps its queries' MFMA A-operands in registers, streams its
+//      chunk in tiles, computes the q.y tile with v_mfma_f32_16x16x4f32,
+//      stages the tile through LDS, and every wave feeds the scores of its
+//      own queries (||y||^2 - 2 q.y for L2, -q.y for inner products; ||x||^2
+//      is constant per query and not needed to rank, Section 5.1) into
+//      register-resident selectors -- distance computation and k-selection in
+//      one kernel, so the distance matrix never reaches HBM;
+//   3. knn_merge_rerank: one wave per query selects the best of the chunks'
+//      partial lists (the second pass of Section 5.3's two-pass selection),
+//      recomputes the kept candidates' distances in the direct form in FP32,
+//      and re-ranks them.  The selection keeps k + 16 candidates (when the
+//      1024-entry queue allows) so that the FP32 cancellation of the norm
+//      decomposition cannot push a true neighbour out of the final k.
+#include "common.hpp"
+#include "kselect.hpp"
+#include "wave_select.hpp"
+
+namespace mk {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kSlack = 16;
+
+// ---------------------------------------------------------------- norms
+__global__ __launch_bounds__(256) void norms_kernel(const float* __restrict__ x, int64_t n,
+                                                    int32_t d, float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float* p = x + i * d;
+    float s = 0.f;
+    if ((d & 3) == 0 && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+        for (int t = 0; t < d; t += 4) {
+            float4 v = *reinterpret_cast<const float4*>(p + t);
+            s = fmaf(v.x, v.x, s);
+            s = fmaf(v.y, v.y, s);
+            s = fmaf(v.z, v.z, s);
+            s = fmaf(v.w, v.w, s);
+        }
+    } else {
+        for (int t = 0; t < d; ++t) s = fmaf(p[t], p[t], s);
+    }
+    out[i] = s;
+}
+
+mk_status launch_norms(const float* x, int64_t n, int32_t d, float* out, hipStream_t s) {
+    if (n == 0) return MK_OK;
+    hipLaunchKernelGGL(norms_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, x, n, d, out);
+    MK_LAUNCHED();
+    return MK_OK;
+}
+
+// ---------------------------------------------------------------- selectors
+// QW independent selectors held by one wave (one per query the wave owns).
+// Merges run one query at a time through a working copy so that the merge
+// network is emitted once, not once per query.
+template <int KR, int T, int QW>
+struct MultiSelect {
+    uint64_t w[QW][KR];
+    uint64_t tq[QW][T];
+    uint64_t kth[QW];
+    float kth_f[QW];
+    int keff;
+
+    __device__ __forceinline__ void init(int k_eff) {
+        keff = k_eff;
+#pragma unroll
+        for (int q = 0; q < QW; ++q) {
+#pragma unroll
+            for (int r = 0; r < KR; ++r) w[q][r] = kSentinel;
+#pragma unroll
+            for (int i = 0; i < T; ++i) tq[q][i] = kSentinel;
+            kth[q] = kSentinel;
+            kth_f[q] = INFINITY;
+        }
+    }
+
+    __device__ __forceinline__ void merge_slot(int q) {
+        uint64_t ww[KR], tt[T];
+#pragma unroll
+        for (int r = 0; r < KR; ++r) ww[r] = opaque(w[0][r]);
+#pragma unroll
+        for (int i = 0; i < T; ++i) tt[i] = opaque(tq[0][i]);
+#pragma unroll
+        for (int qq = 1; qq < QW; ++qq) {
+            const bool hit = qq == q;
+#pragma unroll
+            for (int r = 0; r < KR; ++r) {
+                const uint64_t e = opaque(w[qq][r]);
+                ww[r] = hit ? e : ww[r];
+            }
+#pragma unroll
+            for (int i = 0; i < T; ++i) {
+                const uint64_t e = opaque(tq[qq][i]);
+                tt[i] = hit ? e : tt[i];
+            }
+        }
+        ws_merge<KR, T>(ww, tt);
+        const uint64_t kk = ws_element<KR>(ww, keff - 1);
+        const float kf = kk == kSentinel ? INFINITY : key_score(kk);
+#pragma unroll
+        for (int qq = 0; qq < QW; ++qq) {
+            const bool hit = qq == q;
+#pragma unroll
+            for (int r = 0; r < KR; ++r) w[qq][r] = hit ? opaque(ww[r]) : w[qq][r];
+#pragma unroll
+            for (int i = 0; i < T; ++i) tq[qq][i] = hit ? kSentinel : tq[qq][i];
+            kth[qq] = hit ? kk : kth[qq];
+            kth_f[qq] = hit ? kf : kth_f[qq];
+        }
+    }
+
+    // Offer, for every query q, this lane's candidate (score[q], idx); ok
+    // false means no candidate.  A query whose scores all lose to its current
+    // k-th score is skipped after one compare per lane.
+    __device__ __forceinline__ void offer(const float (&score)[QW], uint32_t idx, bool ok) {
+        uint32_t full = 0;
+#pragma unroll
+        for (int q = 0; q < QW; ++q) {
+            if (__any(ok && score[q] <= kth_f[q])) {
+                const uint64_t key = ok ? make_key(score[q], idx) : kSentinel;
+                const bool take = key < kth[q];
+                if (__any(take)) {
+                    tq_push<T>(tq[q], key, take);
+                    if (__any(tq_full<T>(tq[q]))) full |= 1u << q;
+                }
+            }
+        }
+        while (full) {
+            const int q = __builtin_ctz(full);
+            full &= full - 1;
+            merge_slot(q);
+        }
+    }
+
+    __device__ __forceinline__ void finish() {
+#pragma unroll 1
+        for (int q = 0; q < QW; ++q) merge_slot(q);
+    }
+};
+
+// Kernel shape per queue size: queries per wave QW, waves NW.  The tile is
+// BQ = NW*QW queries by BN = 4096/BQ database rows, i.e. sixteen 16x16 MFMA
+// blocks, each wave owning NBW blocks of a single query block.
+template <int KR>
+struct TileShape;
+template <> struct TileShape<1> { static constexpr int QW = 16, NW = 4; };
+template <> struct TileShape<2> { static constexpr int QW = 8, NW = 4; };
+template <> struct TileShape<4> { static constexpr int QW = 4, NW = 4; };
+template <> struct TileShape<8> { static constexpr int QW = 2, NW = 8; };
+template <> struct TileShape<16> { static constexpr int QW = 2, NW = 8; };
+
+__device__ __forceinline__ float4 load4_guard(const float* __restrict__ row, int dim, int d,
+                                              bool vec, bool ok) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (!ok) return v;
+    if (vec) {
+        if (dim < d) v = *reinterpret_cast<const float4*>(row + dim);
+    } else {
+        if (dim < d) v.x = row[dim];
+        if (dim + 1 < d) v.y = row[dim + 1];
+        if (dim + 2 < d) v.z = row[dim + 2];
+        if (dim + 3 < d) v.w = row[dim + 3];
+    }
+    return v;
+}
+
+// Map hardware workgroup ids (dispatched round-robin over the 8 XCDs) to
+// logical ids so that each XCD runs a contiguous logical range: the
+// workgroups sharing an XCD's L2 then walk the same database chunk.
+__device__ __forceinline__ int64_t xcd_logical_id(int64_t bid, int64_t nblocks) {
+    const int64_t x = bid & 7, pos = bid >> 3;
+    const int64_t base = nblocks >> 3, rem = nblocks & 7;
+    return x * base + (x < rem ? x : rem) + pos;
+}
+
+template <int KR, int DP>
+__global__ __launch_bounds__(64 * TileShape<KR>::NW) void knn_tile_select(
+    const float* __restrict__ xq, int64_t nq, const float* __restrict__ xb,
+    const float* __restrict__ yn, int64_t nb, int32_t d, int32_t vec, int32_t l2,
+    int64_t chunk_len, int32_t nchunks, int32_t nqb, int32_t keff, uint64_t* __restrict__ part) {
+    constexpr int T = SelParams<KR>::T;
+    constexpr int QW = TileShape<KR>::QW;
+    constexpr int NW = TileShape<KR>::NW;
+    constexpr int BQ = NW * QW;
+    constexpr int QB = BQ / 16;
+    constexpr int BN = 4096 / BQ;
+    constexpr int DB = BN / 16;
+    constexpr int NBW = QB * DB / NW;
+    constexpr int NV = BN / 64;
+    constexpr int LDP = BN + 4;
+    constexpr int S4 = DP / 16;
+    static_assert(QB * DB % NW == 0 && DB % NBW == 0, "tile shape");
+
+    __shared__ float dist[BQ * LDP];
+
+    const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)nqb * nchunks);
+    const int64_t chunk = logical / nqb;
+    const int64_t qblk = logical % nqb;
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int li = lane & 15, lh = lane >> 4;
+    const int64_t q0 = qblk * BQ;
+    const int64_t c0 = chunk * chunk_len;
+    const int64_t c1 = c0 + chunk_len < nb ? c0 + chunk_len : nb;
+    const bool use_vec = vec != 0;
+
+    const int my_qb = (wave * NBW) / DB;
+    const int my_db0 = (wave * NBW) % DB;
+
+    // A operand: lane (i, h) holds query i's components 16*s + 4*h + e.
+    float4 areg[S4];
+    {
+        const int64_t q = q0 + my_qb * 16 + li;
+        const bool ok = q < nq;
+        const float* row = xq + (ok ? q : 0) * d;
+#pragma unroll
+        for (int s = 0; s < S4; ++s) areg[s] = load4_guard(row, 16 * s + 4 * lh, d, use_vec, ok);
+    }
+
+    MultiSelect<KR, T, QW> sel;
+    sel.init(keff);
+
+    for (int64_t t0 = c0; t0 < c1; t0 += BN) {
+        floatx4 acc[NBW];
+#pragma unroll
+        for (int j = 0; j < NBW; ++j) {
+            const int64_t yrow = t0 + (my_db0 + j) * 16 + li;
+            const bool ok = yrow < c1;
+            const float* row = xb + (ok ? yrow : 0) * d;
+            float4 b[S4];
+#pragma unroll
+            for (int s = 0; s < S4; ++s) b[s] = load4_guard(row, 16 * s + 4 * lh, d, use_vec, ok);
+            floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < S4; ++s) {
+                c = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[s].x, b[s].x, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[s].y, b[s].y, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[s].z, b[s].z, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[s].w, b[s].w, c, 0, 0, 0);
+            }
+            acc[j] = c;
+        }
+        // D[i][j] of a 16x16 block sits in lane j + 16*(i/4), element i%4.
+#pragma unroll
+        for (int j = 0; j < NBW; ++j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                dist[(my_qb * 16 + 4 * lh + r) * LDP + (my_db0 + j) * 16 + li] = acc[j][r];
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int v = 0; v < NV; ++v) {
+            const int col = v * 64 + lane;
+            const int64_t g = t0 + col;
+            const bool ok = g < c1;
+            const float ynv = (l2 && ok) ? yn[g] : 0.f;
+            float score[QW];
+#pragma unroll
+            for (int qq = 0; qq < QW; ++qq) {
+                const float c = dist[(wave * QW + qq) * LDP + col];
+                score[qq] = l2 ? fmaf(-2.f, c, ynv) : -c;
+            }
+            sel.offer(score, (uint32_t)g, ok);
+        }
+        __syncthreads();
+    }
+    sel.finish();
+
+    constexpr int KS = 64 * KR;
+#pragma unroll
+    for (int qq = 0; qq < QW; ++qq) {
+        const int64_t q = q0 + wave * QW + qq;
+        if (q < nq) {
+            uint64_t* out = part + (q * nchunks + chunk) * KS;
+#pragma unroll
+            for (int r = 0; r < KR; ++r) out[r * 64 + lane] = sel.w[qq][r];
+        }
+    }
+}
+
+// Second pass: merge the chunks' partial lists of one query, recompute the
+// kept candidates' distances in the direct form, re-rank, write k results.
+constexpr int kMergeWaves = 4;
+constexpr int kMaxDim = 512;
+
+template <int KR>
+__global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
+    const uint64_t* __restrict__ part, int32_t nchunks, const float* __restrict__ xq, int64_t nq,
+    const float* __restrict__ xb, int32_t d, int32_t vec, int32_t l2, int32_t k, int32_t keff,
+    float* __restrict__ D, int64_t* __restrict__ I) {
+    constexpr int T = SelParams<KR>::T;
+    constexpr int KS = 64 * KR;
+    __shared__ __align__(16) float xs[kMergeWaves][kMaxDim];
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int64_t q = (int64_t)blockIdx.x * kMergeWaves + wave;
+    if (q >= nq) return;
+
+    WaveSelect<KR, T> ws;
+    ws.init(keff);
+    const uint64_t* p = part + q * nchunks * KS;
+    // Each chunk's list is sorted; only its first keff entries can survive.
+    const int per = (keff + 63) & ~63;
+#pragma unroll 1
+    for (int c = 0; c < nchunks; ++c) {
+#pragma unroll 1
+        for (int e = 0; e < per; e += 64) {
+            const int i = e + lane;
+            if (ws.push(i < keff ? p[(int64_t)c * KS + i] : kSentinel)) ws.merge();
+        }
+    }
+    ws.finish();
+
+    const float* x = xq + q * d;
+    for (int t = lane; t < d; t += 64) xs[wave][t] = x[t];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+
+    uint64_t nk[KR];
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const uint64_t key = ws.w[r];
+        const int e = r * 64 + lane;
+        nk[r] = kSentinel;
+        if (key != kSentinel && e < keff) {
+            const uint32_t i = key_index(key);
+            const float* y = xb + (int64_t)i * d;
+            float s = 0.f;
+            if (vec) {
+                for (int t = 0; t < d; t += 4) {
+                    const float4 yv = *reinterpret_cast<const float4*>(y + t);
+                    const float4 xv = *reinterpret_cast<const float4*>(&xs[wave][t]);
+                    if (l2) {
+                        float a = xv.x - yv.x, b = xv.y - yv.y, c = xv.z - yv.z, dd = xv.w - yv.w;
+                        s = fmaf(a, a, s);
+                        s = fmaf(b, b, s);
+                        s = fmaf(c, c, s);
+                        s = fmaf(dd, dd, s);
+                    } else {
+                        s = fmaf(xv.x, yv.x, s);
+                        s = fmaf(xv.y, yv.y, s);
+                        s = fmaf(xv.z, yv.z, s);
+                        s = fmaf(xv.w, yv.w, s);
+                    }
+                }
+            } else {
+                for (int t = 0; t < d; ++t) {
+                    if (l2) {
+                        const float a = xs[wave][t] - y[t];
+                        s = fmaf(a, a, s);
+                    } else {
+                        s = fmaf(xs[wave][t], y[t], s);
+                    }
+                }
+            }
+            nk[r] = make_key(l2 ? s : -s, i);
+        }
+    }
+    bitonic_sort<false, KR>(nk);
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const int e = r * 64 + lane;
+        if (e < k) {
+            const uint64_t key = nk[r];
+            if (key == kSentinel) {
+                D[q * k + e] = l2 ? INFINITY : -INFINITY;
+                I[q * k + e] = -1;
+            } else {
+                const float s = key_score(key);
+                D[q * k + e] = l2 ? s : -s;
+                I[q * k + e] = (int64_t)key_index(key);
+            }
+        }
+    }
+}
+
+template <int KR, int DP>
+mk_status knn_launch(const float* xq, int64_t nq, const float* xb, const float* yn, int64_t nb,
+                     int32_t d, int32_t k, bool l2, bool vec, float* D, int64_t* I,
+                     hipStream_t stream) {
+    constexpr int QW = TileShape<KR>::QW;
+    constexpr int NW = TileShape<KR>::NW;
+    constexpr int BQ = NW * QW;
+    constexpr int BN = 4096 / BQ;
+    constexpr int KS = 64 * KR;
+    const int keff = k + kSlack < KS ? k + kSlack : KS;
+    const int64_t nqb = ceil_div(nq, BQ);
+    // Chunks: enough workgroups to fill the chip several times over, but
+    // long enough (>= 32 queue lengths) that partial lists stay small.
+    int64_t want = ceil_div(4096, nqb);
+    int64_t max_by_len = nb / (32 * KS) > 1 ? nb / (32 * KS) : 1;
+    int64_t nchunks = want < max_by_len ? want : max_by_len;
+    if (nchunks < 1) nchunks = 1;
+    int64_t chunk_len = ceil_div(ceil_div(nb, nchunks), BN) * BN;
+    if (chunk_len == 0) chunk_len = BN;
+    nchunks = nb > 0 ? ceil_div(nb, chunk_len) : 1;
+
+    Scratch part;
+    mk_status st = part.alloc(sizeof(uint64_t) * (size_t)nq * (size_t)nchunks * KS, stream);
+    if (st != MK_OK) return st;
+    const int64_t nblocks = nqb * nchunks;
+    MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
+    hipLaunchKernelGGL((knn_tile_select<KR, DP>), dim3((unsigned)nblocks), dim3(64 * NW), 0, stream,
+                       xq, nq, xb, yn, nb, d, (int32_t)vec, (int32_t)l2, chunk_len,
+                       (int32_t)nchunks, (int32_t)nqb, keff, part.as<uint64_t>());
+    MK_LAUNCHED();
+    hipLaunchKernelGGL((knn_merge_rerank<KR>), dim3((unsigned)ceil_div(nq, kMergeWaves)),
+                       dim3(64 * kMergeWaves), 0, stream, part.as<uint64_t>(), (int32_t)nchunks,
+                       xq, nq, xb, d, (int32_t)vec, (int32_t)l2, k, keff, D, I);
+    MK_LAUNCHED();
+    return MK_OK;
+}
+
+template <int DP>
+mk_status knn_dispatch_k(const float* xq, int64_t nq, const float* xb, const float* yn,
+                         int64_t nb, int32_t d, int32_t k, bool l2, bool vec, float* D, int64_t* I,
+                         hipStream_t s) {
+    const int want = k + kSlack < kMaxK ? k + kSlack : kMaxK;
+    switch (queue_regs(want)) {
+        case 1: return knn_launch<1, DP>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
+        case 2: return knn_launch<2, DP>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
+        case 4: return knn_launch<4, DP>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
+        case 8: return knn_launch<8, DP>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
+        default: return knn_launch<16, DP>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
+    }
+}
+
+mk_status knn_search(const float* xq, int64_t nq, const float* xb, const float* yn_in, int64_t nb,
+                     int32_t d, int32_t k, mk_metric metric, float* D, int64_t* I,
+                     hipStream_t s) {
+    MK_REQUIRE(nq >= 0 && nb >= 0, MK_ERR_INVALID_ARG, "nq and nb must be >= 0");
+    MK_REQUIRE(d >= 1, MK_ERR_INVALID_ARG, "d must be >= 1");
+    MK_REQUIRE(k >= 1, MK_ERR_INVALID_ARG, "k must be >= 1");
+    MK_REQUIRE(k <= kMaxK, MK_ERR_UNSUPPORTED, "k must be <= 1024");
+    MK_REQUIRE(d <= 256, MK_ERR_UNSUPPORTED, "d must be <= 256");
+    MK_REQUIRE(nb < (1ll << 31), MK_ERR_UNSUPPORTED, "nb must be < 2^31");
+    MK_REQUIRE(metric == MK_METRIC_L2 || metric == MK_METRIC_IP, MK_ERR_INVALID_ARG, "bad metric");
+    if (nq == 0) return MK_OK;
+    MK_REQUIRE(xq && D && I && (xb || nb == 0), MK_ERR_INVALID_ARG, "null pointer");
+    const bool l2 = metric == MK_METRIC_L2;
+    const bool vec = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(xq) % 16 == 0) &&
+                     (reinterpret_cast<uintptr_t>(xb) % 16 == 0);
+    Scratch norms;
+    const float* yn = yn_in;
+    if (l2 && !yn && nb > 0) {
+        mk_status st = norms.alloc(sizeof(float) * (size_t)nb, s);
+        if (st != MK_OK) return st;
+        st = launch_norms(xb, nb, d, norms.as<float>(), s);
+        if (st != MK_OK) return st;
+        yn = norms.as<float>();
+    }
+    if (d <= 32) return knn_dispatch_k<32>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
+    if (d <= 64) return knn_dispatch_k<64>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
+    if (d <= 96) return knn_dispatch_k<96>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
+    if (d <= 128) return knn_dispatch_k<128>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
+    return knn_dispatch_k<256>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
+}
+
+}  // namespace mk
+
+extern "C" mk_status mk_norms(const float* x, int64_t n, int32_t d, float* out,
+                              mk_stream_t stream) {
+    MK_REQUIRE(n >= 0 && d >= 1, MK_ERR_INVALID_ARG, "n must be >= 0 and d >= 1");
+    if (n == 0) return MK_OK;
+    MK_REQUIRE(x && out, MK_ERR_INVALID_ARG, "null pointer");
+    return mk::launch_norms(x, n, d, out, static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_knn_search(const float* xq, int64_t nq, const float* xb, int64_t nb,
+                                   int32_t d, int32_t k, mk_metric metric, float* D, int64_t* I,
+                                   mk_stream_t stream) {
+    return mk::knn_search(xq, nq, xb, nullptr, nb, d, k, metric, D, I,
+                          static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_knn_search_prenorm(const float* xq, int64_t nq, const float* xb,
+                                           const float* yn, int64_t nb, int32_t d, int32_t k,
+                                           mk_metric metric, float* D, int64_t* I,
+                                           mk_stream_t stream) {
+    MK_REQUIRE(metric != MK_METRIC_L2 || yn || nb == 0, MK_ERR_INVALID_ARG,
+               "L2 search needs the database norms");
+    return mk::knn_search(xq, nq, xb, yn, nb, d, k, metric, D, I,
+                          static_cast<hipStream_t>(stream));
+}

@@ -1,0 +1,213 @@
+// Row-wise k-selection of a resident matrix (Section 2 problem statement,
+// Section 4.2 selection, Section 6.1 benchmark shape) and the generic merge of
+// per-segment partial results (the second pass of the two-pass k-selection of
+// Section 5.3).
+//
+// Pass 1: one wave per (row, segment) streams the segment once with 16-byte
+// coalesced loads and feeds WaveSelect.  A row that fits one segment writes
+// its final result directly; otherwise the wave writes its k best keys and
+// pass 2 (one wave per row) selects over the segments' keys.
+#include "common.hpp"
+#include "kselect.hpp"
+#include "wave_select.hpp"
+
+namespace mk {
+
+namespace {
+
+constexpr int kWavesPerBlock = 4;
+
+template <bool LARGEST>
+__device__ __forceinline__ uint64_t value_key(float v, uint32_t idx) {
+    return make_key(LARGEST ? -v : v, idx);
+}
+
+// Write the first k keys of a lane-stride queue as (value, index) pairs.
+template <int KR, bool LARGEST>
+__device__ __forceinline__ void emit_values(const uint64_t (&w)[KR], int k, float* vals,
+                                            int64_t* idx) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const int e = r * 64 + lane;
+        if (e < k) {
+            const uint64_t key = w[r];
+            if (key == kSentinel) {
+                vals[e] = LARGEST ? -INFINITY : INFINITY;
+                idx[e] = -1;
+            } else {
+                const float s = key_score(key);
+                vals[e] = LARGEST ? -s : s;
+                idx[e] = (int64_t)key_index(key);
+            }
+        }
+    }
+}
+
+template <int KR>
+__device__ __forceinline__ void emit_keys(const uint64_t (&w)[KR], int k, uint64_t* out) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const int e = r * 64 + lane;
+        if (e < k) out[e] = w[r];
+    }
+}
+
+template <int KR, int T, bool LARGEST>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_pass1(
+    const float* __restrict__ a, int64_t nrows, int64_t len, int32_t k, int32_t nseg,
+    int64_t seg_len, float* __restrict__ vals, int64_t* __restrict__ idx,
+    uint64_t* __restrict__ partial) {
+    constexpr int U = 4;  // float4 loads in flight per lane
+    __shared__ float stage[kWavesPerBlock][4 * U][64];
+    const int wave = threadIdx.x / 64;
+    const int lane = lane_id();
+    const int64_t unit = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    if (unit >= nrows * (int64_t)nseg) return;  // wave-uniform
+    const int64_t row = unit / nseg;
+    const int64_t seg = unit % nseg;
+    const int64_t lo = seg * seg_len;
+    const int64_t hi = lo + seg_len < len ? lo + seg_len : len;
+    const float* rp = a + row * len;
+
+    WaveSelect<KR, T> ws;
+    ws.init(k);
+
+    // Vector body over 16-byte aligned rows: lane takes 4 consecutive values
+    // per load, U loads in flight.  Most groups are rejected by one compare
+    // per value against the current k-th score; a group with any candidate
+    // is staged in LDS and offered value by value from a single loop, so the
+    // merge network appears once in the kernel.
+    const bool aligned = (reinterpret_cast<uintptr_t>(rp + lo) & 15) == 0;
+    const int64_t vec_end = aligned ? lo + ((hi - lo) / (256 * U)) * (256 * U) : lo;
+    for (int64_t e = lo; e < vec_end; e += 256 * U) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            v[u] = *reinterpret_cast<const float4*>(rp + e + u * 256 + lane * 4);
+        bool cand = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            cand |= ws.may_take(LARGEST ? -v[u].x : v[u].x);
+            cand |= ws.may_take(LARGEST ? -v[u].y : v[u].y);
+            cand |= ws.may_take(LARGEST ? -v[u].z : v[u].z);
+            cand |= ws.may_take(LARGEST ? -v[u].w : v[u].w);
+        }
+        if (__any(cand)) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                stage[wave][4 * u + 0][lane] = v[u].x;
+                stage[wave][4 * u + 1][lane] = v[u].y;
+                stage[wave][4 * u + 2][lane] = v[u].z;
+                stage[wave][4 * u + 3][lane] = v[u].w;
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+            for (int j = 0; j < 4 * U; ++j) {
+                const float val = stage[wave][j][lane];
+                const uint32_t i = (uint32_t)(e + (j >> 2) * 256 + lane * 4 + (j & 3));
+                if (ws.push(value_key<LARGEST>(val, i))) ws.merge();
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    // Scalar remainder (and unaligned rows): one value per lane per step.
+#pragma unroll 1
+    for (int64_t e = vec_end; e < hi; e += 64) {
+        const int64_t i = e + lane;
+        const uint64_t key = i < hi ? value_key<LARGEST>(rp[i], (uint32_t)i) : kSentinel;
+        if (ws.push(key)) ws.merge();
+    }
+    ws.finish();
+    if (nseg == 1) {
+        emit_values<KR, LARGEST>(ws.w, k, vals + row * k, idx + row * k);
+    } else {
+        emit_keys<KR>(ws.w, k, partial + unit * k);
+    }
+}
+
+// Pass 2: per row, select the k best of nseg * k partial keys.
+template <int KR, int T, bool LARGEST>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_merge(
+    const uint64_t* __restrict__ partial, int64_t nrows, int32_t nseg, int32_t k,
+    float* __restrict__ vals, int64_t* __restrict__ idx) {
+    const int wave = threadIdx.x / 64;
+    const int lane = lane_id();
+    const int64_t row = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    if (row >= nrows) return;
+    const uint64_t* p = partial + row * (int64_t)nseg * k;
+    const int64_t n = (int64_t)nseg * k;
+    WaveSelect<KR, T> ws;
+    ws.init(k);
+#pragma unroll 1
+    for (int64_t e = 0; e < n; e += 64) {
+        const int64_t i = e + lane;
+        if (ws.push(i < n ? p[i] : kSentinel)) ws.merge();
+    }
+    ws.finish();
+    emit_values<KR, LARGEST>(ws.w, k, vals + row * k, idx + row * k);
+}
+
+template <int KR, int T, bool LARGEST>
+mk_status kselect_launch(const float* a, int64_t nrows, int64_t len, int32_t k, float* vals,
+                         int64_t* idx, hipStream_t stream) {
+    constexpr int KS = 64 * KR;
+    // Enough waves to fill the chip, but segments long enough that the
+    // partial keys stay a small fraction of the input.
+    int64_t want = ceil_div(8192, nrows > 0 ? nrows : 1);
+    int64_t max_by_len = len / (int64_t)(16 * KS > 4096 ? 16 * KS : 4096);
+    int64_t nseg = want < max_by_len ? want : max_by_len;
+    if (nseg < 1) nseg = 1;
+    if (nseg > 4096) nseg = 4096;
+    int64_t seg_len = ceil_div(ceil_div(len, nseg), 256) * 256;
+    nseg = len > 0 ? ceil_div(len, seg_len) : 1;
+    if (seg_len == 0) seg_len = 256;
+
+    Scratch part;
+    if (nseg > 1) {
+        mk_status st = part.alloc(sizeof(uint64_t) * (size_t)nrows * (size_t)nseg * (size_t)k, stream);
+        if (st != MK_OK) return st;
+    }
+    const int64_t units = nrows * nseg;
+    hipLaunchKernelGGL((kselect_pass1<KR, T, LARGEST>), dim3((unsigned)ceil_div(units, kWavesPerBlock)),
+                       dim3(64 * kWavesPerBlock), 0, stream, a, nrows, len, k, (int32_t)nseg,
+                       seg_len, vals, idx, part.as<uint64_t>());
+    MK_LAUNCHED();
+    if (nseg > 1) {
+        hipLaunchKernelGGL((kselect_merge<KR, T, LARGEST>),
+                           dim3((unsigned)ceil_div(nrows, kWavesPerBlock)), dim3(64 * kWavesPerBlock),
+                           0, stream, part.as<uint64_t>(), nrows, (int32_t)nseg, k, vals, idx);
+        MK_LAUNCHED();
+    }
+    return MK_OK;
+}
+
+template <bool LARGEST>
+mk_status kselect_dispatch(const float* a, int64_t nrows, int64_t len, int32_t k, float* vals,
+                           int64_t* idx, hipStream_t s) {
+    switch (queue_regs(k)) {
+        case 1: return kselect_launch<1, SelParams<1>::T, LARGEST>(a, nrows, len, k, vals, idx, s);
+        case 2: return kselect_launch<2, SelParams<2>::T, LARGEST>(a, nrows, len, k, vals, idx, s);
+        case 4: return kselect_launch<4, SelParams<4>::T, LARGEST>(a, nrows, len, k, vals, idx, s);
+        case 8: return kselect_launch<8, SelParams<8>::T, LARGEST>(a, nrows, len, k, vals, idx, s);
+        default: return kselect_launch<16, SelParams<16>::T, LARGEST>(a, nrows, len, k, vals, idx, s);
+    }
+}
+
+}  // namespace
+
+}  // namespace mk
+
+extern "C" mk_status mk_kselect(const float* a, int64_t nrows, int64_t len, int32_t k,
+                                int32_t largest, float* vals, int64_t* idx, mk_stream_t stream) {
+    MK_REQUIRE(nrows >= 0 && len >= 0, MK_ERR_INVALID_ARG, "nrows and len must be >= 0");
+    MK_REQUIRE(k >= 1, MK_ERR_INVALID_ARG, "k must be >= 1");
+    MK_REQUIRE(k <= mk::kMaxK, MK_ERR_UNSUPPORTED, "k must be <= 1024");
+    MK_REQUIRE(len < (int64_t)0xFFFFFFFF, MK_ERR_UNSUPPORTED, "rows must be shorter than 2^32-1");
+    if (nrows == 0) return MK_OK;
+    MK_REQUIRE(vals && idx && (a || len == 0), MK_ERR_INVALID_ARG, "null pointer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return largest ? mk::kselect_dispatch<true>(a, nrows, len, k, vals, idx, s)
+                   : mk::kselect_dispatch<false>(a, nrows, len, k, vals, idx, s);
+}

@@ -16,9 +16,9 @@ nearest even):
   training draws, which use their own seeds.
 * ``uniform_rows(nrows, length, seed)``: U[0, 1) float32 rows (k-selection
   benchmark input).
-* Large draws are split into chunks of ``CHUNK`` rows, chunk i seeded by
-  ``SeedSequence(seed).spawn`` child i, so any chunk can be regenerated alone
-  and chunks are drawn on several threads.
+* Large draws are split into chunks of max(1, 2^22 // columns) rows, chunk i
+  seeded by ``SeedSequence(seed).spawn`` child i, so any chunk can be
+  regenerated alone and chunks are drawn on several threads.
 """
 from __future__ import annotations
 
@@ -27,7 +27,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
-CHUNK = 1 << 20
+CHUNK_ELEMS = 1 << 22
 
 
 def _threads() -> int:
@@ -36,12 +36,13 @@ def _threads() -> int:
 
 def _chunked(n: int, d: int, seed: int, fill) -> np.ndarray:
     out = np.empty((n, d), np.float32)
-    nchunks = (n + CHUNK - 1) // CHUNK
+    rows = max(1, CHUNK_ELEMS // max(d, 1))
+    nchunks = (n + rows - 1) // rows
     children = np.random.SeedSequence(seed).spawn(max(nchunks, 1))
 
     def work(i):
-        lo = i * CHUNK
-        hi = min(n, lo + CHUNK)
+        lo = i * rows
+        hi = min(n, lo + rows)
         rng = np.random.Generator(np.random.PCG64(children[i]))
         fill(rng, out[lo:hi])
 
@@ -109,3 +110,22 @@ SEED = {"exact_small": 101, "exact_large": 102, "ivfpq": 103, "mixed": 104, "lea
 def pq_init_rows(n: int, M: int, seed: int) -> np.ndarray:
     """[M, 256] Forgy rows for the M sub-quantizers (seed + m each)."""
     return np.stack([choose_rows(n, 256, seed + m) for m in range(M)])
+
+
+# ---------------------------------------------------------------- workloads
+# Each workload draws its arrays from SeedSequence entropy (base, offset).
+def exact_small():
+    """50,000 x 64 N(0, 1) database, 500 queries of the same law, k = 10."""
+    return {"xb": gaussian(50_000, 64, (101, 0)), "xq": gaussian(500, 64, (101, 1)), "k": 10}
+
+
+def exact_large(nb: int = 1_000_000, nq: int = 10_000):
+    """1,000-component mixture in d = 128: database and queries."""
+    mix = Mixture(1000, 128, (102, 99))
+    return {"xb": mix.sample(nb, (102, 0)), "xq": mix.sample(nq, (102, 1)),
+            "ks": (1, 32, 256, 1024)}
+
+
+def kselect_rows(nrows: int = 10_000, length: int = 128_000):
+    """Row-wise k-selection input: U[0, 1) float32 rows."""
+    return uniform_rows(nrows, length, (106, 0))
