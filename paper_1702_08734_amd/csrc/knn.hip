@@ -149,7 +149,7 @@ struct MultiSelect {
 // blocks, each wave owning NBW blocks of a single query block.
 template <int KR>
 struct TileShape;
-template <> struct TileShape<1> { static constexpr int QW = 16, NW = 4; };
+template <> struct TileShape<1> { static constexpr int QW = 8, NW = 8; };
 template <> struct TileShape<2> { static constexpr int QW = 8, NW = 4; };
 template <> struct TileShape<4> { static constexpr int QW = 4, NW = 4; };
 template <> struct TileShape<8> { static constexpr int QW = 2, NW = 8; };
