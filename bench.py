@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Benchmark of the exact brute-force k-NN hot path on one MI355X.
+
+Workload (synthetic, seeded): a 1,000,000 x 128 float32 database drawn from a
+1,000-component Gaussian mixture and 10,000 queries of the same law; one step
+is one L2 search of all queries for each k in {1, 32, 256, 1024} (database
+norms, fused MFMA distance tiles + register k-selection, chunk merge and
+direct-form re-rank).  The metric is TFLOP/s at 2 flop per multiply-add of
+the q.y term, 2 * nq * nb * d per search.
+
+Prints ONE JSON line.  Inputs are resident in device memory before timing
+starts.  `roofline` reports the dominant kernel (knn_tile_select) timed with
+HIP events inside the library over the timed steps; `cpu_baseline` times the
+float64 oracle on a bounded sample of the same queries on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+FP32_MFMA_PEAK_TFLOPS = 157.3
+KS = (1, 32, 256, 1024)
+PMC_FILE = os.path.join(ROOT, "profiles", "knn_tile_select_exact_large_pmc.json")
+KERNEL_SOURCES = ["knn.hip", "wave_select.hpp", "kselect.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1702_08734_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_counters(launch_flops_per_byte=None):
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE counters, if they were taken on this source."""
+    try:
+        with open(PMC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(xq, xb, target_s: float):
+    import numpy as np
+    import oracle
+    d = xq.shape[1]
+    nb = xb.shape[0]
+    n = 16
+    t0 = time.perf_counter()
+    oracle.knn(xq[:n], xb, 32)
+    dt = time.perf_counter() - t0
+    n2 = int(max(16, min(2000, n * target_s / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.knn(xq[n:n + n2], xb, 32)
+    dt2 = time.perf_counter() - t0
+    return {
+        "value": 2.0 * n2 * nb * d / dt2 / 1e12,
+        "unit": "TFLOP/s",
+        "cores": oracle.get_threads(),
+        "kind": "oracle",
+        "sample": f"{n2} of {xq.shape[0]} queries against the full {nb}-row database, k=32 "
+                  f"(float64 direct-form distances + full sort per query; {dt2:.1f} s)",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are "
+              "not part of this build", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1702_08734_amd import api, synth
+
+    w = synth.exact_large()
+    xq_h, xb_h = w["xq"], w["xb"]
+    nq, d = xq_h.shape
+    nb = xb_h.shape[0]
+    xq = torch.from_numpy(xq_h).cuda()
+    xb = torch.from_numpy(xb_h).cuda()
+    torch.cuda.synchronize()
+
+    def step():
+        for k in KS:
+            api.knn_search(xq, xb, k)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # per-k timing (not part of the reported value)
+    per_k = {}
+    for k in KS:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.knn_search(xq, xb, k)
+        torch.cuda.synchronize()
+        per_k[str(k)] = round((time.perf_counter() - t0) * 1e3, 3)
+
+    api.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    api.profile_enable(False)
+    tile_ms, tile_n = api.profile_read("knn_tile_select")
+    merge_ms, merge_n = api.profile_read("knn_merge_rerank")
+
+    flops_search = 2.0 * nq * nb * d
+    flops_step = flops_search * len(KS)
+    value = flops_step * args.steps / elapsed / 1e12
+    achieved = flops_search * tile_n / (tile_ms / 1e3) / 1e12 if tile_ms > 0 else None
+    traffic = traffic_from_counters()
+    out = {
+        "metric": "brute-force k-NN TFLOP/s (exact L2, fused MFMA distance + k-selection)",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "exact_large: 1,000,000 x 128 float32 database from a 1,000-component "
+                        "Gaussian mixture, 10,000 queries, L2, one search per k in "
+                        "{1, 32, 256, 1024}",
+            "nb": nb, "nq": nq, "d": d, "ks": list(KS),
+        },
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "knn_tile_select",
+            "achieved": round(achieved, 3) if achieved else None,
+            "peak": FP32_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4) if achieved else None,
+            "traffic": traffic,
+            "launch_ms_avg": round(tile_ms / max(tile_n, 1), 4),
+            "launches": tile_n,
+        },
+        "extra": {
+            "per_k_ms": per_k,
+            "merge_rerank_ms_avg": round(merge_ms / max(merge_n, 1), 4),
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(xq_h, xb_h, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

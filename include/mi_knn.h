@@ -89,7 +89,7 @@ mk_status mk_kselect(const float* a, int64_t nrows, int64_t len, int32_t k, int3
  * The selection keeps extra candidates beyond k (up to the 1024-entry
  * selector) and re-ranks them by the direct form, which removes the
  * cancellation error of ||x||^2 + ||y||^2 - 2<x,y>.  nb must be < 2^31.
- * Supported d: 1..512.
+ * Supported d: 1..256.
  */
 mk_status mk_knn_search(const float* xq, int64_t nq, const float* xb, int64_t nb, int32_t d,
                         int32_t k, mk_metric metric, float* D, int64_t* I, mk_stream_t stream);
@@ -210,6 +210,23 @@ mk_status mk_ivfpq_set_quantizers(mk_ivfpq* index, const float* coarse, const fl
  */
 mk_status mk_ivfpq_get_lists(const mk_ivfpq* index, int64_t* offsets, uint8_t* codes,
                              int64_t* ids);
+
+
+/* ------------------------------------------------------------------------
+ * Kernel timing.  While enabled, every launch of the library's main kernels
+ * is bracketed by a pair of HIP events recorded on the launch stream, so the
+ * measured time is that kernel's own execution on the device.
+ * ------------------------------------------------------------------------ */
+
+/* on != 0 starts recording (and clears earlier records); 0 stops. */
+mk_status mk_profile_enable(int32_t on);
+
+/*
+ * Total device time in milliseconds and number of launches recorded for the
+ * kernel called `name` (e.g. "knn_tile_select", "kselect_pass1",
+ * "ivf_scan"); waits for the recorded events.  Unknown names give 0 and 0.
+ */
+mk_status mk_profile_read(const char* name, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

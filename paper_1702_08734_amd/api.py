@@ -53,6 +53,8 @@ _SIGS = {
     "mk_ivfpq_get_quantizers": [_vp, _vp, _vp],
     "mk_ivfpq_set_quantizers": [_vp, _vp, _vp, _vp],
     "mk_ivfpq_get_lists": [_vp, _vp, _vp, _vp],
+    "mk_profile_enable": [_i32],
+    "mk_profile_read": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)],
 }
 _RESTYPE = {"mk_last_error": ctypes.c_char_p, "mk_ivfpq_destroy": None,
             "mk_ivfpq_ntotal": ctypes.c_int64}
@@ -238,3 +240,16 @@ class IVFPQ:
         ids = np.empty(max(n, 1), np.int64)
         _call("mk_ivfpq_get_lists", self._h, offs.ctypes.data, codes.ctypes.data, ids.ctypes.data)
         return offs, codes[:n], ids[:n]
+
+
+def profile_enable(on: bool = True) -> None:
+    """Start (clearing earlier records) or stop per-launch kernel timing."""
+    _call("mk_profile_enable", int(bool(on)))
+
+
+def profile_read(name: str):
+    """(total device milliseconds, launches) recorded for kernel `name`."""
+    ms = ctypes.c_double()
+    n = _i64()
+    _call("mk_profile_read", name.encode(), ctypes.byref(ms), ctypes.byref(n))
+    return ms.value, n.value

@@ -19,6 +19,7 @@
 //      decomposition cannot push a true neighbour out of the final k.
 #include "common.hpp"
 #include "kselect.hpp"
+#include "profile.hpp"
 #include "wave_select.hpp"
 
 namespace mk {
@@ -406,14 +407,21 @@ mk_status knn_launch(const float* xq, int64_t nq, const float* xb, const float* 
     if (st != MK_OK) return st;
     const int64_t nblocks = nqb * nchunks;
     MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
-    hipLaunchKernelGGL((knn_tile_select<KR, DP>), dim3((unsigned)nblocks), dim3(64 * NW), 0, stream,
-                       xq, nq, xb, yn, nb, d, (int32_t)vec, (int32_t)l2, chunk_len,
-                       (int32_t)nchunks, (int32_t)nqb, keff, part.as<uint64_t>());
-    MK_LAUNCHED();
-    hipLaunchKernelGGL((knn_merge_rerank<KR>), dim3((unsigned)ceil_div(nq, kMergeWaves)),
-                       dim3(64 * kMergeWaves), 0, stream, part.as<uint64_t>(), (int32_t)nchunks,
-                       xq, nq, xb, d, (int32_t)vec, (int32_t)l2, k, keff, D, I);
-    MK_LAUNCHED();
+    {
+        ProfScope prof("knn_tile_select", stream);
+        hipLaunchKernelGGL((knn_tile_select<KR, DP>), dim3((unsigned)nblocks), dim3(64 * NW), 0,
+                           stream, xq, nq, xb, yn, nb, d, (int32_t)vec, (int32_t)l2, chunk_len,
+                           (int32_t)nchunks, (int32_t)nqb, keff, part.as<uint64_t>());
+        MK_LAUNCHED();
+    }
+    {
+        ProfScope prof("knn_merge_rerank", stream);
+        hipLaunchKernelGGL((knn_merge_rerank<KR>), dim3((unsigned)ceil_div(nq, kMergeWaves)),
+                           dim3(64 * kMergeWaves), 0, stream, part.as<uint64_t>(),
+                           (int32_t)nchunks, xq, nq, xb, d, (int32_t)vec, (int32_t)l2, k, keff, D,
+                           I);
+        MK_LAUNCHED();
+    }
     return MK_OK;
 }
 

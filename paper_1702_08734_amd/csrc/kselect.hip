@@ -9,6 +9,7 @@
 // pass 2 (one wave per row) selects over the segments' keys.
 #include "common.hpp"
 #include "kselect.hpp"
+#include "profile.hpp"
 #include "wave_select.hpp"
 
 namespace mk {
@@ -170,10 +171,14 @@ mk_status kselect_launch(const float* a, int64_t nrows, int64_t len, int32_t k, 
         if (st != MK_OK) return st;
     }
     const int64_t units = nrows * nseg;
-    hipLaunchKernelGGL((kselect_pass1<KR, T, LARGEST>), dim3((unsigned)ceil_div(units, kWavesPerBlock)),
-                       dim3(64 * kWavesPerBlock), 0, stream, a, nrows, len, k, (int32_t)nseg,
-                       seg_len, vals, idx, part.as<uint64_t>());
-    MK_LAUNCHED();
+    {
+        ProfScope prof("kselect_pass1", stream);
+        hipLaunchKernelGGL((kselect_pass1<KR, T, LARGEST>),
+                           dim3((unsigned)ceil_div(units, kWavesPerBlock)),
+                           dim3(64 * kWavesPerBlock), 0, stream, a, nrows, len, k, (int32_t)nseg,
+                           seg_len, vals, idx, part.as<uint64_t>());
+        MK_LAUNCHED();
+    }
     if (nseg > 1) {
         hipLaunchKernelGGL((kselect_merge<KR, T, LARGEST>),
                            dim3((unsigned)ceil_div(nrows, kWavesPerBlock)), dim3(64 * kWavesPerBlock),
