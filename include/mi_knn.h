@@ -124,8 +124,7 @@ mk_status mk_kmeans_assign(const float* x, int64_t n, int32_t d, const float* c,
  * floor(count_b / 2) of b's count.
  *   x [n, d], assign [n] int64 in [0, K), c [K, d] float32 in/out,
  *   counts [K] int64 out (may be NULL).
- * Synchronises the stream (the empty-cluster rule reads the counts on the
- * host).
+ * Every step, the empty-cluster rule included, runs on the device.
  */
 mk_status mk_kmeans_update(const float* x, int64_t n, int32_t d, const int64_t* assign,
                            int32_t K, float* c, int64_t* counts, mk_stream_t stream);
@@ -182,7 +181,9 @@ int64_t mk_ivfpq_ntotal(const mk_ivfpq* index);
  * coarse centroids (Eq. 5), scan their lists with PQ lookup tables built
  * from the three-term split of Eq. 11 and staged in LDS, select the k
  * nearest of the scanned entries (Eq. 6).  D are ADC squared distances
- * (FP32), I the ids.  1 <= nprobe <= min(nlist, 1024).
+ * (FP32), I the ids.  1 <= nprobe <= min(nlist, 1024).  The tables and the
+ * per-list merge buffers must fit 64 KiB of LDS: 1024 M + 32 k <= 65536
+ * bytes (any k for M <= 32, k <= 256 for M = 64).
  *   xq [nq, d] float32, D [nq, k] float32, I [nq, k] int64
  */
 mk_status mk_ivfpq_search(mk_ivfpq* index, const float* xq, int64_t nq, int32_t k,

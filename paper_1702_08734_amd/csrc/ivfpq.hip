@@ -1,44 +1,833 @@
-// IVFADC index: training, adding and searching (filled in below).
+// IVFADC index (Section 2 Eq. 3-6, Section 5.2-5.3): k-means training of the
+// coarse quantizer and of the product quantizer, encoding and list building,
+// and the search: coarse exact search (Eq. 5), query tables of term 3, the
+// list scan with per-(query, list) lookup tables in LDS feeding WaveSelect,
+// and the merge of the per-list partial results (Eq. 6).
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
 #include "common.hpp"
+#include "kselect.hpp"
+#include "profile.hpp"
+#include "wave_select.hpp"
 
 struct mk_ivfpq {
-    int32_t d, nlist, M;
+    int32_t d = 0, nlist = 0, M = 0, dsub = 0;
+    bool trained = false;
+    float* coarse = nullptr;        // [nlist, d]
+    float* coarse_norms = nullptr;  // [nlist]
+    float* books = nullptr;         // [M, 256, dsub]
+    float* term1 = nullptr;         // [nlist, M, 256]
+    int64_t ntotal = 0;
+    int64_t capacity = 0;
+    uint8_t* codes = nullptr;       // [capacity, M], grouped by list
+    int64_t* ids = nullptr;         // [capacity]
+    int64_t* offsets_dev = nullptr; // [nlist + 1]
+    std::vector<int64_t> offsets;   // host copy
 };
 
-extern "C" mk_status mk_kmeans_assign(const float*, int64_t, int32_t, const float*, int32_t,
-                                      int64_t*, float*, mk_stream_t) {
-    MK_REQUIRE(false, MK_ERR_UNSUPPORTED, "not built yet");
+namespace mk {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+void free_dev(void*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
 }
-extern "C" mk_status mk_kmeans_update(const float*, int64_t, int32_t, const int64_t*, int32_t,
-                                      float*, int64_t*, mk_stream_t) {
-    MK_REQUIRE(false, MK_ERR_UNSUPPORTED, "not built yet");
+
+template <class T>
+mk_status alloc_dev(T*& p, size_t count) {
+    void* v = nullptr;
+    MK_HIP(hipMalloc(&v, sizeof(T) * (count ? count : 1)));
+    p = static_cast<T*>(v);
+    return MK_OK;
 }
-extern "C" mk_status mk_pq_encode(const float*, int64_t, int32_t, int32_t, const float*, uint8_t*,
-                                  mk_stream_t) {
-    MK_REQUIRE(false, MK_ERR_UNSUPPORTED, "not built yet");
+
+#define MK_TRY(expr)                  \
+    do {                              \
+        mk_status st_ = (expr);       \
+        if (st_ != MK_OK) return st_; \
+    } while (0)
+
+// ---------------------------------------------------------------- k-means
+__global__ void gather_rows_kernel(const float* __restrict__ src, int32_t d,
+                                   const int64_t* __restrict__ rows, int64_t n,
+                                   float* __restrict__ dst) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= n * d) return;
+    const int64_t i = g / d, t = g % d;
+    dst[g] = src[rows[i] * d + t];
 }
-extern "C" mk_status mk_ivfpq_create(int32_t, int32_t, int32_t, mk_ivfpq**) {
-    MK_REQUIRE(false, MK_ERR_UNSUPPORTED, "not built yet");
+
+// Sum points into their centroid's FP64 accumulator (one thread per
+// coordinate, so neighbouring lanes add to neighbouring addresses).
+__global__ void km_accumulate(const float* __restrict__ x, int64_t n, int32_t d,
+                              const int64_t* __restrict__ assign, double* __restrict__ sums,
+                              unsigned long long* __restrict__ counts) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= n * d) return;
+    const int64_t i = g / d, t = g % d;
+    const int64_t a = assign[i];
+    if (t == 0) atomicAdd(&counts[a], 1ull);
+    atomicAdd(&sums[a * d + t], (double)x[g]);
 }
-extern "C" void mk_ivfpq_destroy(mk_ivfpq* p) { delete p; }
-extern "C" mk_status mk_ivfpq_train(mk_ivfpq*, const float*, int64_t, int32_t, const int64_t*,
-                                    const int64_t*, mk_stream_t) {
-    MK_REQUIRE(false, MK_ERR_UNSUPPORTED, "not built yet");
+
+__global__ void km_finalize(const double* __restrict__ sums,
+                            const unsigned long long* __restrict__ counts, int32_t K, int32_t d,
+                            float* __restrict__ c, int64_t* __restrict__ counts_out) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= (int64_t)K * d) return;
+    const int64_t j = g / d, t = g % d;
+    const unsigned long long n = counts[j];
+    if (n > 0) c[g] = (float)(sums[g] / (double)n);
+    if (t == 0) counts_out[j] = (int64_t)n;
 }
-extern "C" mk_status mk_ivfpq_add(mk_ivfpq*, const float*, int64_t, mk_stream_t) {
-    MK_REQUIRE(false, MK_ERR_UNSUPPORTED, "not built yet");
+
+// Empty clusters, in increasing index order, split the currently largest
+// cluster (ties to the lower index): multiplicative offsets 1 +- 2^-10 with
+// alternating sign per coordinate, products in FP64 rounded to FP32, and the
+// empty cluster takes floor(count / 2).  One workgroup walks the clusters.
+__global__ __launch_bounds__(kBlock) void km_split_empty(float* __restrict__ c,
+                                                         int64_t* __restrict__ counts, int32_t K,
+                                                         int32_t d) {
+    __shared__ int64_t s_cnt[kBlock];
+    __shared__ int32_t s_idx[kBlock];
+    __shared__ int32_t s_j;
+    const int tid = threadIdx.x;
+    int32_t j = 0;
+    for (;;) {
+        if (tid == 0) {
+            while (j < K && counts[j] != 0) ++j;
+            s_j = j;
+        }
+        __syncthreads();
+        j = s_j;
+        if (j >= K) break;
+        int64_t best = -1;
+        int32_t bi = 0;
+        for (int32_t q = tid; q < K; q += kBlock) {
+            const int64_t v = counts[q];
+            if (v > best) {
+                best = v;
+                bi = q;
+            }
+        }
+        s_cnt[tid] = best;
+        s_idx[tid] = bi;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (tid < w) {
+                const int64_t o = s_cnt[tid + w];
+                const int32_t oi = s_idx[tid + w];
+                if (o > s_cnt[tid] || (o == s_cnt[tid] && oi < s_idx[tid])) {
+                    s_cnt[tid] = o;
+                    s_idx[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        const int32_t b = s_idx[0];
+        const double eps = 1.0 / 1024.0;
+        for (int32_t t = tid; t < d; t += kBlock) {
+            const double s = (t % 2 == 0) ? 1.0 : -1.0;
+            const double v = (double)c[(int64_t)b * d + t];
+            c[(int64_t)j * d + t] = (float)(v * (1.0 + s * eps));
+            c[(int64_t)b * d + t] = (float)(v * (1.0 - s * eps));
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const int64_t half = counts[b] / 2;
+            counts[j] = half;
+            counts[b] -= half;
+        }
+        __syncthreads();
+        ++j;
+    }
 }
-extern "C" int64_t mk_ivfpq_ntotal(const mk_ivfpq*) { return 0; }
-extern "C" mk_status mk_ivfpq_search(mk_ivfpq*, const float*, int64_t, int32_t, int32_t, float*,
-                                     int64_t*, mk_stream_t) {
-    MK_REQUIRE(false, MK_ERR_UNSUPPORTED, "not built yet");
+
+mk_status kmeans_update(const float* x, int64_t n, int32_t d, const int64_t* assign, int32_t K,
+                        float* c, int64_t* counts_out, hipStream_t s) {
+    Scratch sums, cnt, cnt64;
+    MK_TRY(sums.alloc(sizeof(double) * (size_t)K * d, s));
+    MK_TRY(cnt.alloc(sizeof(unsigned long long) * (size_t)K, s));
+    int64_t* counts = counts_out;
+    if (!counts) {
+        MK_TRY(cnt64.alloc(sizeof(int64_t) * (size_t)K, s));
+        counts = cnt64.as<int64_t>();
+    }
+    MK_HIP(hipMemsetAsync(sums.ptr, 0, sizeof(double) * (size_t)K * d, s));
+    MK_HIP(hipMemsetAsync(cnt.ptr, 0, sizeof(unsigned long long) * (size_t)K, s));
+    if (n > 0) {
+        hipLaunchKernelGGL(km_accumulate, dim3((unsigned)ceil_div(n * d, kBlock)), dim3(kBlock), 0,
+                           s, x, n, d, assign, sums.as<double>(), cnt.as<unsigned long long>());
+        MK_LAUNCHED();
+    }
+    hipLaunchKernelGGL(km_finalize, dim3((unsigned)ceil_div((int64_t)K * d, kBlock)), dim3(kBlock),
+                       0, s, sums.as<double>(), cnt.as<unsigned long long>(), K, d, c, counts);
+    MK_LAUNCHED();
+    hipLaunchKernelGGL(km_split_empty, dim3(1), dim3(kBlock), 0, s, c, counts, K, d);
+    MK_LAUNCHED();
+    return MK_OK;
 }
-extern "C" mk_status mk_ivfpq_get_quantizers(const mk_ivfpq*, float*, float*) {
-    MK_REQUIRE(false, MK_ERR_UNSUPPORTED, "not built yet");
+
+mk_status kmeans_assign(const float* x, int64_t n, int32_t d, const float* c, int32_t K,
+                        int64_t* assign, float* dist, hipStream_t s) {
+    Scratch dtmp;
+    float* D = dist;
+    if (!D) {
+        MK_TRY(dtmp.alloc(sizeof(float) * (size_t)(n > 0 ? n : 1), s));
+        D = dtmp.as<float>();
+    }
+    return knn_search(x, n, c, nullptr, K, d, 1, MK_METRIC_L2, D, assign, s);
 }
-extern "C" mk_status mk_ivfpq_set_quantizers(mk_ivfpq*, const float*, const float*, mk_stream_t) {
-    MK_REQUIRE(false, MK_ERR_UNSUPPORTED, "not built yet");
+
+// Lloyd iterations on c [K, d], initialised by the caller.
+mk_status kmeans_run(const float* x, int64_t n, int32_t d, float* c, int32_t K, int32_t niter,
+                     hipStream_t s) {
+    Scratch a;
+    MK_TRY(a.alloc(sizeof(int64_t) * (size_t)n, s));
+    for (int32_t it = 0; it < niter; ++it) {
+        MK_TRY(kmeans_assign(x, n, d, c, K, a.as<int64_t>(), nullptr, s));
+        MK_TRY(kmeans_update(x, n, d, a.as<int64_t>(), K, c, nullptr, s));
+    }
+    return MK_OK;
 }
-extern "C" mk_status mk_ivfpq_get_lists(const mk_ivfpq*, int64_t*, uint8_t*, int64_t*) {
-    MK_REQUIRE(false, MK_ERR_UNSUPPORTED, "not built yet");
+
+// ---------------------------------------------------------------- PQ encode
+template <int DS>
+__global__ __launch_bounds__(kBlock) void pq_encode_fixed(const float* __restrict__ r, int64_t n,
+                                                          int32_t d, int32_t M,
+                                                          const float* __restrict__ books,
+                                                          uint8_t* __restrict__ codes) {
+    __shared__ float cb[256 * DS];
+    const int m = blockIdx.y;
+    for (int e = threadIdx.x; e < 256 * DS; e += kBlock) cb[e] = books[(int64_t)m * 256 * DS + e];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    float rv[DS];
+#pragma unroll
+    for (int t = 0; t < DS; ++t) rv[t] = r[i * d + (int64_t)m * DS + t];
+    float best = INFINITY;
+    int arg = 0;
+    for (int j = 0; j < 256; ++j) {
+        float s = 0.f;
+#pragma unroll
+        for (int t = 0; t < DS; ++t) {
+            const float df = rv[t] - cb[j * DS + t];
+            s = fmaf(df, df, s);
+        }
+        if (s < best) {  // strict: ties keep the lower index
+            best = s;
+            arg = j;
+        }
+    }
+    codes[i * M + m] = (uint8_t)arg;
+}
+
+__global__ __launch_bounds__(kBlock) void pq_encode_any(const float* __restrict__ r, int64_t n,
+                                                        int32_t d, int32_t M, int32_t ds,
+                                                        const float* __restrict__ books,
+                                                        uint8_t* __restrict__ codes) {
+    extern __shared__ float cbs[];
+    const int m = blockIdx.y;
+    for (int e = threadIdx.x; e < 256 * ds; e += kBlock) cbs[e] = books[(int64_t)m * 256 * ds + e];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const float* rv = r + i * d + (int64_t)m * ds;
+    float best = INFINITY;
+    int arg = 0;
+    for (int j = 0; j < 256; ++j) {
+        float s = 0.f;
+        for (int t = 0; t < ds; ++t) {
+            const float df = rv[t] - cbs[j * ds + t];
+            s = fmaf(df, df, s);
+        }
+        if (s < best) {
+            best = s;
+            arg = j;
+        }
+    }
+    codes[i * M + m] = (uint8_t)arg;
+}
+
+mk_status pq_encode(const float* r, int64_t n, int32_t d, int32_t M, const float* books,
+                    uint8_t* codes, hipStream_t s) {
+    if (n == 0) return MK_OK;
+    const int32_t ds = d / M;
+    const dim3 grid((unsigned)ceil_div(n, kBlock), (unsigned)M), block(kBlock);
+    switch (ds) {
+        case 1: hipLaunchKernelGGL(pq_encode_fixed<1>, grid, block, 0, s, r, n, d, M, books, codes); break;
+        case 2: hipLaunchKernelGGL(pq_encode_fixed<2>, grid, block, 0, s, r, n, d, M, books, codes); break;
+        case 4: hipLaunchKernelGGL(pq_encode_fixed<4>, grid, block, 0, s, r, n, d, M, books, codes); break;
+        case 8: hipLaunchKernelGGL(pq_encode_fixed<8>, grid, block, 0, s, r, n, d, M, books, codes); break;
+        case 16: hipLaunchKernelGGL(pq_encode_fixed<16>, grid, block, 0, s, r, n, d, M, books, codes); break;
+        default:
+            hipLaunchKernelGGL(pq_encode_any, grid, block, sizeof(float) * 256 * ds, s, r, n, d, M,
+                               ds, books, codes);
+            break;
+    }
+    MK_LAUNCHED();
+    return MK_OK;
+}
+
+// ---------------------------------------------------------------- helpers
+// r[i] = x[i] - c[list[i]]  (FP32)
+__global__ void residual_kernel(const float* __restrict__ x, int64_t n, int32_t d,
+                                const float* __restrict__ c, const int64_t* __restrict__ list,
+                                float* __restrict__ r) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= n * d) return;
+    const int64_t i = g / d, t = g % d;
+    r[g] = x[g] - c[list[i] * d + t];
+}
+
+// dst[i, :] = src[i, off : off + w]
+__global__ void columns_kernel(const float* __restrict__ src, int64_t n, int32_t d, int32_t off,
+                               int32_t w, float* __restrict__ dst) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= n * w) return;
+    const int64_t i = g / w, t = g % w;
+    dst[g] = src[i * d + off + t];
+}
+
+// term1[L, m, j] = ||c_{m,j}||^2 + 2 <c_L^m, c_{m,j}>   (Eq. 11, term 1)
+__global__ void term1_kernel(const float* __restrict__ coarse, const float* __restrict__ books,
+                             int32_t nlist, int32_t M, int32_t ds, float* __restrict__ term1) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= (int64_t)nlist * M * 256) return;
+    const int64_t L = g / (M * 256);
+    const int32_t m = (int32_t)((g / 256) % M), j = (int32_t)(g % 256);
+    const float* cw = books + ((int64_t)m * 256 + j) * ds;
+    const float* cl = coarse + L * (int64_t)M * ds + (int64_t)m * ds;
+    float nn = 0.f, ip = 0.f;
+    for (int t = 0; t < ds; ++t) {
+        nn = fmaf(cw[t], cw[t], nn);
+        ip = fmaf(cl[t], cw[t], ip);
+    }
+    term1[g] = fmaf(2.f, ip, nn);
+}
+
+// term3[q, m, j] = <x_q^m, c_{m,j}>   (Eq. 11, term 3)
+__global__ void term3_kernel(const float* __restrict__ xq, int64_t nq, int32_t M, int32_t ds,
+                             const float* __restrict__ books, float* __restrict__ term3) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= nq * M * 256) return;
+    const int64_t q = g / (M * 256);
+    const int32_t m = (int32_t)((g / 256) % M), j = (int32_t)(g % 256);
+    const float* cw = books + ((int64_t)m * 256 + j) * ds;
+    const float* x = xq + q * (int64_t)M * ds + (int64_t)m * ds;
+    float ip = 0.f;
+    for (int t = 0; t < ds; ++t) ip = fmaf(x[t], cw[t], ip);
+    term3[g] = ip;
+}
+
+__global__ void histogram_kernel(const int64_t* __restrict__ list, int64_t n,
+                                 unsigned long long* __restrict__ counts) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&counts[list[i]], 1ull);
+}
+
+__global__ void to_key_kernel(const int64_t* __restrict__ list, int64_t n,
+                              uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        key[i] = (uint32_t)list[i];
+        val[i] = (uint32_t)i;
+    }
+}
+
+// Old entries of list L move from old_off[L] + e to new_off[L] + e.
+__global__ void move_old_kernel(const int64_t* __restrict__ old_off,
+                                const int64_t* __restrict__ new_off, int32_t M,
+                                const uint8_t* __restrict__ old_codes,
+                                const int64_t* __restrict__ old_ids, uint8_t* __restrict__ codes,
+                                int64_t* __restrict__ ids) {
+    const int32_t L = blockIdx.x;
+    const int64_t lo = old_off[L], n = old_off[L + 1] - lo, dst = new_off[L];
+    for (int64_t e = threadIdx.x; e < n; e += kBlock) {
+        ids[dst + e] = old_ids[lo + e];
+        for (int m = 0; m < M; ++m) codes[(dst + e) * M + m] = old_codes[(lo + e) * M + m];
+    }
+}
+
+// New entry p of the list-sorted batch (original row perm[p], list key[p])
+// goes after the list's old entries, in batch order.
+__global__ void place_new_kernel(const uint32_t* __restrict__ key, const uint32_t* __restrict__ perm,
+                                 int64_t nb, const int64_t* __restrict__ new_off,
+                                 const int64_t* __restrict__ old_off,
+                                 const int64_t* __restrict__ batch_off, int32_t M,
+                                 const uint8_t* __restrict__ batch_codes, int64_t id0,
+                                 uint8_t* __restrict__ codes, int64_t* __restrict__ ids) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= nb) return;
+    const uint32_t L = key[p];
+    const int64_t i = perm[p];
+    const int64_t pos = new_off[L] + (old_off[L + 1] - old_off[L]) + (p - batch_off[L]);
+    ids[pos] = id0 + i;
+    for (int m = 0; m < M; ++m) codes[pos * M + m] = batch_codes[i * M + m];
+}
+
+// ---------------------------------------------------------------- list scan
+constexpr int kScanWaves = 4;
+
+// One workgroup per (query, probe rank).  The list's lookup tables
+// LUT[m][j] = term1[L][m][j] - 2 term3[q][m][j] are staged in LDS; each lane
+// takes one code at a time (coalesced 16-byte loads when M is a multiple of
+// 16), sums term2 + sum_m LUT[m][code_m] (Eq. 10 via Eq. 11) and offers it
+// to its wave's selector keyed by (distance, offset in list) -- offset order
+// is id order inside a list.  The four waves' queues are merged through LDS
+// and the winners' ids resolved (Section 5.3: ids only for the selected).
+template <int KR>
+__global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
+    const float* __restrict__ term1, const float* __restrict__ term3,
+    const float* __restrict__ coarse_d, const int64_t* __restrict__ coarse_i,
+    const int64_t* __restrict__ offsets, const uint8_t* __restrict__ codes,
+    const int64_t* __restrict__ ids, int32_t M, int32_t nprobe, int32_t k,
+    uint64_t* __restrict__ part) {
+    constexpr int T = SelParams<KR>::T;
+    constexpr int KS = 64 * KR;
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* lut = reinterpret_cast<float*>(smem);
+    uint64_t* qbuf = reinterpret_cast<uint64_t*>(smem + (size_t)M * 256 * sizeof(float));
+
+    const int64_t item = blockIdx.x;
+    const int64_t q = item / nprobe;
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int64_t L = coarse_i[item];
+    const float term2 = coarse_d[item];
+    uint64_t* out = part + item * k;
+
+    if (L < 0) {  // fewer lists than probes: nothing to scan (wave-uniform)
+        for (int e = threadIdx.x; e < k; e += 64 * kScanWaves) out[e] = kSentinel;
+        return;
+    }
+    const float* t1 = term1 + L * (int64_t)M * 256;
+    const float* t3 = term3 + q * (int64_t)M * 256;
+    for (int e = threadIdx.x; e < M * 256; e += 64 * kScanWaves) lut[e] = fmaf(-2.f, t3[e], t1[e]);
+    __syncthreads();
+
+    const int64_t lo = offsets[L];
+    const int64_t n = offsets[L + 1] - lo;
+    const uint8_t* lc = codes + lo * M;
+
+    WaveSelect<KR, T> ws;
+    ws.init(k);
+    const bool vec16 = (M & 15) == 0;
+#pragma unroll 1
+    for (int64_t e0 = (int64_t)wave * 64; e0 < n; e0 += 64 * kScanWaves) {
+        const int64_t e = e0 + lane;
+        float dist = term2;
+        const bool ok = e < n;
+        if (ok) {
+            const uint8_t* c = lc + e * M;
+            if (vec16) {
+                for (int m0 = 0; m0 < M; m0 += 16) {
+                    const uint4 w = *reinterpret_cast<const uint4*>(c + m0);
+                    const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const int m = m0 + 4 * h + b;
+                            dist += lut[m * 256 + ((ww[h] >> (8 * b)) & 0xFF)];
+                        }
+                    }
+                }
+            } else {
+                for (int m0 = 0; m0 < M; m0 += 4) {
+                    const uint32_t w = *reinterpret_cast<const uint32_t*>(c + m0);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) dist += lut[(m0 + b) * 256 + ((w >> (8 * b)) & 0xFF)];
+                }
+            }
+        }
+        const uint64_t key = ok ? make_key(dist, (uint32_t)e) : kSentinel;
+        if (ws.push(key)) ws.merge();
+    }
+    ws.finish();
+
+    // merge the waves' queues: each publishes its first k keys
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const int e = r * 64 + lane;
+        if (e < k) qbuf[wave * k + e] = ws.w[r];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        WaveSelect<KR, T> fin;
+        fin.init(k);
+        const int tot = kScanWaves * k;
+#pragma unroll 1
+        for (int e0 = 0; e0 < tot; e0 += 64) {
+            const int e = e0 + lane;
+            if (fin.push(e < tot ? qbuf[e] : kSentinel)) fin.merge();
+        }
+        fin.finish();
+#pragma unroll
+        for (int r = 0; r < KR; ++r) {
+            const int e = r * 64 + lane;
+            if (e < k) {
+                const uint64_t key = fin.w[r];
+                out[e] = key == kSentinel
+                             ? kSentinel
+                             : ((key & 0xFFFFFFFF00000000ull) | (uint32_t)ids[lo + key_index(key)]);
+            }
+        }
+    }
+}
+
+mk_status launch_scan(const float* term1, const float* term3, const float* cd, const int64_t* ci,
+                      const int64_t* offsets, const uint8_t* codes, const int64_t* ids, int32_t M,
+                      int64_t nq, int32_t nprobe, int32_t k, uint64_t* part, hipStream_t s) {
+    const int64_t items = nq * nprobe;
+    if (items == 0) return MK_OK;
+    MK_REQUIRE(items < (1ll << 31), MK_ERR_UNSUPPORTED, "nq * nprobe too large for one launch");
+    const size_t shm = (size_t)M * 256 * sizeof(float) + (size_t)kScanWaves * k * sizeof(uint64_t);
+    MK_REQUIRE(shm <= 65536, MK_ERR_UNSUPPORTED,
+               "lookup tables plus merge buffers exceed 64 KiB of LDS (reduce M or k)");
+    const dim3 grid((unsigned)items), block(64 * kScanWaves);
+    ProfScope prof("ivf_scan", s);
+    switch (queue_regs(k)) {
+        case 1: hipLaunchKernelGGL(ivf_scan<1>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part); break;
+        case 2: hipLaunchKernelGGL(ivf_scan<2>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part); break;
+        case 4: hipLaunchKernelGGL(ivf_scan<4>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part); break;
+        case 8: hipLaunchKernelGGL(ivf_scan<8>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part); break;
+        default: hipLaunchKernelGGL(ivf_scan<16>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part); break;
+    }
+    MK_LAUNCHED();
+    return MK_OK;
+}
+
+unsigned grid_of(int64_t n) { return (unsigned)ceil_div(n > 0 ? n : 1, kBlock); }
+
+mk_status build_term1(mk_ivfpq* ix, hipStream_t s) {
+    free_dev(reinterpret_cast<void*&>(ix->term1));
+    MK_TRY(alloc_dev(ix->term1, (size_t)ix->nlist * ix->M * 256));
+    hipLaunchKernelGGL(term1_kernel, dim3(grid_of((int64_t)ix->nlist * ix->M * 256)), dim3(kBlock),
+                       0, s, ix->coarse, ix->books, ix->nlist, ix->M, ix->dsub, ix->term1);
+    MK_LAUNCHED();
+    return launch_norms(ix->coarse, ix->nlist, ix->d, ix->coarse_norms, s);
+}
+
+void reset_lists(mk_ivfpq* ix) {
+    free_dev(reinterpret_cast<void*&>(ix->codes));
+    free_dev(reinterpret_cast<void*&>(ix->ids));
+    ix->ntotal = 0;
+    ix->capacity = 0;
+    ix->offsets.assign(ix->nlist + 1, 0);
+}
+
+mk_status upload_offsets(mk_ivfpq* ix, hipStream_t s) {
+    if (!ix->offsets_dev) MK_TRY(alloc_dev(ix->offsets_dev, ix->nlist + 1));
+    MK_HIP(hipMemcpyAsync(ix->offsets_dev, ix->offsets.data(), sizeof(int64_t) * (ix->nlist + 1),
+                          hipMemcpyHostToDevice, s));
+    MK_HIP(hipStreamSynchronize(s));
+    return MK_OK;
+}
+
+mk_status alloc_quantizers(mk_ivfpq* ix) {
+    if (!ix->coarse) MK_TRY(alloc_dev(ix->coarse, (size_t)ix->nlist * ix->d));
+    if (!ix->coarse_norms) MK_TRY(alloc_dev(ix->coarse_norms, (size_t)ix->nlist));
+    if (!ix->books) MK_TRY(alloc_dev(ix->books, (size_t)ix->M * 256 * ix->dsub));
+    return MK_OK;
+}
+
+mk_status train(mk_ivfpq* ix, const float* xt, int64_t nt, int32_t niter,
+                const int64_t* coarse_rows, const int64_t* pq_rows, hipStream_t s) {
+    const int32_t d = ix->d, nlist = ix->nlist, M = ix->M, ds = ix->dsub;
+    MK_TRY(alloc_quantizers(ix));
+    Scratch rows, assign, res, sub;
+    MK_TRY(rows.alloc(sizeof(int64_t) * (size_t)std::max<int64_t>(nlist, 256), s));
+    // coarse quantizer
+    MK_HIP(hipMemcpyAsync(rows.ptr, coarse_rows, sizeof(int64_t) * nlist, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_of((int64_t)nlist * d)), dim3(kBlock), 0, s,
+                       xt, d, rows.as<int64_t>(), (int64_t)nlist, ix->coarse);
+    MK_LAUNCHED();
+    MK_TRY(kmeans_run(xt, nt, d, ix->coarse, nlist, niter, s));
+    // residuals of the training set to the final coarse centroids
+    MK_TRY(assign.alloc(sizeof(int64_t) * (size_t)nt, s));
+    MK_TRY(res.alloc(sizeof(float) * (size_t)nt * d, s));
+    MK_TRY(sub.alloc(sizeof(float) * (size_t)nt * ds, s));
+    MK_TRY(kmeans_assign(xt, nt, d, ix->coarse, nlist, assign.as<int64_t>(), nullptr, s));
+    hipLaunchKernelGGL(residual_kernel, dim3(grid_of(nt * d)), dim3(kBlock), 0, s, xt, nt, d,
+                       ix->coarse, assign.as<int64_t>(), res.as<float>());
+    MK_LAUNCHED();
+    // M independent sub-quantizers of 256 centroids on contiguous sub-vectors
+    for (int32_t m = 0; m < M; ++m) {
+        hipLaunchKernelGGL(columns_kernel, dim3(grid_of(nt * ds)), dim3(kBlock), 0, s,
+                           res.as<float>(), nt, d, m * ds, ds, sub.as<float>());
+        MK_LAUNCHED();
+        float* cm = ix->books + (int64_t)m * 256 * ds;
+        MK_HIP(hipMemcpyAsync(rows.ptr, pq_rows + (int64_t)m * 256, sizeof(int64_t) * 256,
+                              hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_of(256 * ds)), dim3(kBlock), 0, s,
+                           sub.as<float>(), ds, rows.as<int64_t>(), (int64_t)256, cm);
+        MK_LAUNCHED();
+        MK_TRY(kmeans_run(sub.as<float>(), nt, ds, cm, 256, niter, s));
+    }
+    MK_TRY(build_term1(ix, s));
+    reset_lists(ix);
+    MK_TRY(upload_offsets(ix, s));
+    ix->trained = true;
+    return MK_OK;
+}
+
+mk_status add(mk_ivfpq* ix, const float* xb, int64_t nb, hipStream_t s) {
+    const int32_t d = ix->d, nlist = ix->nlist, M = ix->M;
+    if (nb == 0) return MK_OK;
+    Scratch list, res, bcodes, cnt, keys, vals, keys2, vals2, tmp, oldoff, newoff, boff;
+    MK_TRY(list.alloc(sizeof(int64_t) * nb, s));
+    MK_TRY(res.alloc(sizeof(float) * nb * d, s));
+    MK_TRY(bcodes.alloc((size_t)nb * M, s));
+    MK_TRY(kmeans_assign(xb, nb, d, ix->coarse, nlist, list.as<int64_t>(), nullptr, s));
+    hipLaunchKernelGGL(residual_kernel, dim3(grid_of(nb * d)), dim3(kBlock), 0, s, xb, nb, d,
+                       ix->coarse, list.as<int64_t>(), res.as<float>());
+    MK_LAUNCHED();
+    MK_TRY(pq_encode(res.as<float>(), nb, d, M, ix->books, bcodes.as<uint8_t>(), s));
+    // per-list counts of the batch
+    MK_TRY(cnt.alloc(sizeof(unsigned long long) * nlist, s));
+    MK_HIP(hipMemsetAsync(cnt.ptr, 0, sizeof(unsigned long long) * nlist, s));
+    hipLaunchKernelGGL(histogram_kernel, dim3(grid_of(nb)), dim3(kBlock), 0, s,
+                       list.as<int64_t>(), nb, cnt.as<unsigned long long>());
+    MK_LAUNCHED();
+    std::vector<unsigned long long> hc(nlist);
+    MK_HIP(hipMemcpyAsync(hc.data(), cnt.ptr, sizeof(unsigned long long) * nlist,
+                          hipMemcpyDeviceToHost, s));
+    // stable order of the batch by list (radix sort is stable)
+    MK_TRY(keys.alloc(sizeof(uint32_t) * nb, s));
+    MK_TRY(vals.alloc(sizeof(uint32_t) * nb, s));
+    MK_TRY(keys2.alloc(sizeof(uint32_t) * nb, s));
+    MK_TRY(vals2.alloc(sizeof(uint32_t) * nb, s));
+    hipLaunchKernelGGL(to_key_kernel, dim3(grid_of(nb)), dim3(kBlock), 0, s, list.as<int64_t>(),
+                       nb, keys.as<uint32_t>(), vals.as<uint32_t>());
+    MK_LAUNCHED();
+    int end_bit = 1;
+    while ((1ll << end_bit) < nlist) ++end_bit;
+    size_t tmp_bytes = 0;
+    MK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys.as<uint32_t>(),
+                                              keys2.as<uint32_t>(), vals.as<uint32_t>(),
+                                              vals2.as<uint32_t>(), (int)nb, 0, end_bit, s));
+    MK_TRY(tmp.alloc(tmp_bytes, s));
+    MK_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.ptr, tmp_bytes, keys.as<uint32_t>(),
+                                              keys2.as<uint32_t>(), vals.as<uint32_t>(),
+                                              vals2.as<uint32_t>(), (int)nb, 0, end_bit, s));
+    MK_HIP(hipStreamSynchronize(s));
+    // new CSR offsets (host bookkeeping of nlist + 1 integers)
+    std::vector<int64_t> bo(nlist + 1, 0), no(nlist + 1, 0);
+    for (int32_t L = 0; L < nlist; ++L) {
+        bo[L + 1] = bo[L] + (int64_t)hc[L];
+        no[L + 1] = no[L] + (ix->offsets[L + 1] - ix->offsets[L]) + (int64_t)hc[L];
+    }
+    const int64_t total = no[nlist];
+    uint8_t* ncodes = nullptr;
+    int64_t* nids = nullptr;
+    MK_TRY(alloc_dev(ncodes, (size_t)total * M));
+    MK_TRY(alloc_dev(nids, (size_t)total));
+    MK_TRY(oldoff.alloc(sizeof(int64_t) * (nlist + 1), s));
+    MK_TRY(newoff.alloc(sizeof(int64_t) * (nlist + 1), s));
+    MK_TRY(boff.alloc(sizeof(int64_t) * (nlist + 1), s));
+    MK_HIP(hipMemcpyAsync(oldoff.ptr, ix->offsets.data(), sizeof(int64_t) * (nlist + 1),
+                          hipMemcpyHostToDevice, s));
+    MK_HIP(hipMemcpyAsync(newoff.ptr, no.data(), sizeof(int64_t) * (nlist + 1),
+                          hipMemcpyHostToDevice, s));
+    MK_HIP(hipMemcpyAsync(boff.ptr, bo.data(), sizeof(int64_t) * (nlist + 1),
+                          hipMemcpyHostToDevice, s));
+    if (ix->ntotal > 0) {
+        hipLaunchKernelGGL(move_old_kernel, dim3(nlist), dim3(kBlock), 0, s, oldoff.as<int64_t>(),
+                           newoff.as<int64_t>(), M, ix->codes, ix->ids, ncodes, nids);
+        MK_LAUNCHED();
+    }
+    hipLaunchKernelGGL(place_new_kernel, dim3(grid_of(nb)), dim3(kBlock), 0, s,
+                       keys2.as<uint32_t>(), vals2.as<uint32_t>(), nb, newoff.as<int64_t>(),
+                       oldoff.as<int64_t>(), boff.as<int64_t>(), M, bcodes.as<uint8_t>(),
+                       ix->ntotal, ncodes, nids);
+    MK_LAUNCHED();
+    MK_HIP(hipStreamSynchronize(s));
+    free_dev(reinterpret_cast<void*&>(ix->codes));
+    free_dev(reinterpret_cast<void*&>(ix->ids));
+    ix->codes = ncodes;
+    ix->ids = nids;
+    ix->capacity = total;
+    ix->ntotal = total;
+    ix->offsets = no;
+    return upload_offsets(ix, s);
+}
+
+mk_status search(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t k, int32_t nprobe, float* D,
+                 int64_t* I, hipStream_t s) {
+    const int32_t M = ix->M;
+    Scratch cd, ci, t3, part;
+    MK_TRY(cd.alloc(sizeof(float) * nq * nprobe, s));
+    MK_TRY(ci.alloc(sizeof(int64_t) * nq * nprobe, s));
+    MK_TRY(t3.alloc(sizeof(float) * nq * M * 256, s));
+    MK_TRY(part.alloc(sizeof(uint64_t) * nq * nprobe * k, s));
+    // Eq. 5: probe set and term 2 by exact search over the coarse centroids
+    MK_TRY(knn_search(xq, nq, ix->coarse, ix->coarse_norms, ix->nlist, ix->d, nprobe,
+                      MK_METRIC_L2, cd.as<float>(), ci.as<int64_t>(), s));
+    // term 3 per query
+    hipLaunchKernelGGL(term3_kernel, dim3(grid_of(nq * M * 256)), dim3(kBlock), 0, s, xq, nq, M,
+                       ix->dsub, ix->books, t3.as<float>());
+    MK_LAUNCHED();
+    MK_TRY(launch_scan(ix->term1, t3.as<float>(), cd.as<float>(), ci.as<int64_t>(),
+                       ix->offsets_dev, ix->codes, ix->ids, M, nq, nprobe, k,
+                       part.as<uint64_t>(), s));
+    ProfScope prof("ivf_merge", s);
+    return merge_key_lists(part.as<uint64_t>(), nq, nprobe, k, D, I, s);
+}
+
+}  // namespace
+
+}  // namespace mk
+
+// ---------------------------------------------------------------- C ABI
+extern "C" mk_status mk_kmeans_assign(const float* x, int64_t n, int32_t d, const float* c,
+                                      int32_t K, int64_t* assign, float* dist,
+                                      mk_stream_t stream) {
+    MK_REQUIRE(n >= 0 && d >= 1 && K >= 1, MK_ERR_INVALID_ARG, "need n >= 0, d >= 1, K >= 1");
+    if (n == 0) return MK_OK;
+    MK_REQUIRE(x && c && assign, MK_ERR_INVALID_ARG, "null pointer");
+    return mk::kmeans_assign(x, n, d, c, K, assign, dist, static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_kmeans_update(const float* x, int64_t n, int32_t d, const int64_t* assign,
+                                      int32_t K, float* c, int64_t* counts, mk_stream_t stream) {
+    MK_REQUIRE(n >= 0 && d >= 1 && K >= 1, MK_ERR_INVALID_ARG, "need n >= 0, d >= 1, K >= 1");
+    MK_REQUIRE(c && (n == 0 || (x && assign)), MK_ERR_INVALID_ARG, "null pointer");
+    return mk::kmeans_update(x, n, d, assign, K, c, counts, static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_pq_encode(const float* r, int64_t n, int32_t d, int32_t M,
+                                  const float* codebooks, uint8_t* codes, mk_stream_t stream) {
+    MK_REQUIRE(n >= 0 && d >= 1 && M >= 1 && d % M == 0 && d / M <= 64, MK_ERR_INVALID_ARG,
+               "need d % M == 0 and d / M <= 64");
+    if (n == 0) return MK_OK;
+    MK_REQUIRE(r && codebooks && codes, MK_ERR_INVALID_ARG, "null pointer");
+    return mk::pq_encode(r, n, d, M, codebooks, codes, static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_ivfpq_create(int32_t d, int32_t nlist, int32_t M, mk_ivfpq** out) {
+    MK_REQUIRE(out, MK_ERR_INVALID_ARG, "null output pointer");
+    MK_REQUIRE(d >= 1 && d <= 256, MK_ERR_UNSUPPORTED, "d must be in [1, 256]");
+    MK_REQUIRE(nlist >= 1 && nlist <= (1 << 24), MK_ERR_INVALID_ARG, "nlist must be in [1, 2^24]");
+    MK_REQUIRE(M >= 4 && M <= 64 && M % 4 == 0, MK_ERR_UNSUPPORTED,
+               "M must be a multiple of 4 in [4, 64]");
+    MK_REQUIRE(d % M == 0, MK_ERR_INVALID_ARG, "d must be a multiple of M");
+    mk_ivfpq* ix = new (std::nothrow) mk_ivfpq();
+    MK_REQUIRE(ix, MK_ERR_OOM, "host allocation failed");
+    ix->d = d;
+    ix->nlist = nlist;
+    ix->M = M;
+    ix->dsub = d / M;
+    ix->offsets.assign(nlist + 1, 0);
+    *out = ix;
+    return MK_OK;
+}
+
+extern "C" void mk_ivfpq_destroy(mk_ivfpq* ix) {
+    if (!ix) return;
+    mk::free_dev(reinterpret_cast<void*&>(ix->coarse));
+    mk::free_dev(reinterpret_cast<void*&>(ix->coarse_norms));
+    mk::free_dev(reinterpret_cast<void*&>(ix->books));
+    mk::free_dev(reinterpret_cast<void*&>(ix->term1));
+    mk::free_dev(reinterpret_cast<void*&>(ix->codes));
+    mk::free_dev(reinterpret_cast<void*&>(ix->ids));
+    mk::free_dev(reinterpret_cast<void*&>(ix->offsets_dev));
+    delete ix;
+}
+
+extern "C" mk_status mk_ivfpq_train(mk_ivfpq* ix, const float* xt, int64_t nt, int32_t niter,
+                                    const int64_t* coarse_init_rows, const int64_t* pq_init_rows,
+                                    mk_stream_t stream) {
+    MK_REQUIRE(ix && xt && coarse_init_rows && pq_init_rows, MK_ERR_INVALID_ARG, "null pointer");
+    MK_REQUIRE(nt >= ix->nlist && nt >= 256, MK_ERR_INVALID_ARG, "need nt >= nlist and nt >= 256");
+    MK_REQUIRE(niter >= 0, MK_ERR_INVALID_ARG, "niter must be >= 0");
+    MK_REQUIRE(nt < (1ll << 31), MK_ERR_UNSUPPORTED, "nt must be < 2^31");
+    for (int32_t i = 0; i < ix->nlist; ++i)
+        MK_REQUIRE(coarse_init_rows[i] >= 0 && coarse_init_rows[i] < nt, MK_ERR_INVALID_ARG,
+                   "coarse init row out of range");
+    for (int64_t i = 0; i < (int64_t)ix->M * 256; ++i)
+        MK_REQUIRE(pq_init_rows[i] >= 0 && pq_init_rows[i] < nt, MK_ERR_INVALID_ARG,
+                   "PQ init row out of range");
+    return mk::train(ix, xt, nt, niter, coarse_init_rows, pq_init_rows,
+                     static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_ivfpq_add(mk_ivfpq* ix, const float* xb, int64_t nb, mk_stream_t stream) {
+    MK_REQUIRE(ix, MK_ERR_INVALID_ARG, "null index");
+    MK_REQUIRE(ix->trained, MK_ERR_STATE, "index is not trained");
+    MK_REQUIRE(nb >= 0, MK_ERR_INVALID_ARG, "nb must be >= 0");
+    MK_REQUIRE(nb == 0 || xb, MK_ERR_INVALID_ARG, "null pointer");
+    MK_REQUIRE(ix->ntotal + nb < 0xFFFFFFFFll, MK_ERR_UNSUPPORTED,
+               "an index holds fewer than 2^32 - 1 vectors");
+    return mk::add(ix, xb, nb, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int64_t mk_ivfpq_ntotal(const mk_ivfpq* ix) { return ix ? ix->ntotal : 0; }
+
+extern "C" mk_status mk_ivfpq_search(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t k,
+                                     int32_t nprobe, float* D, int64_t* I, mk_stream_t stream) {
+    MK_REQUIRE(ix, MK_ERR_INVALID_ARG, "null index");
+    MK_REQUIRE(ix->trained, MK_ERR_STATE, "index is not trained");
+    MK_REQUIRE(nq >= 0, MK_ERR_INVALID_ARG, "nq must be >= 0");
+    MK_REQUIRE(k >= 1, MK_ERR_INVALID_ARG, "k must be >= 1");
+    MK_REQUIRE(k <= mk::kMaxK, MK_ERR_UNSUPPORTED, "k must be <= 1024");
+    MK_REQUIRE(nprobe >= 1 && nprobe <= ix->nlist && nprobe <= mk::kMaxK, MK_ERR_INVALID_ARG,
+               "need 1 <= nprobe <= min(nlist, 1024)");
+    if (nq == 0) return MK_OK;
+    MK_REQUIRE(xq && D && I, MK_ERR_INVALID_ARG, "null pointer");
+    return mk::search(ix, xq, nq, k, nprobe, D, I, static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_ivfpq_get_quantizers(const mk_ivfpq* ix, float* coarse, float* codebooks) {
+    MK_REQUIRE(ix, MK_ERR_INVALID_ARG, "null index");
+    MK_REQUIRE(ix->trained, MK_ERR_STATE, "index is not trained");
+    MK_HIP(hipDeviceSynchronize());
+    if (coarse)
+        MK_HIP(hipMemcpy(coarse, ix->coarse, sizeof(float) * (size_t)ix->nlist * ix->d,
+                         hipMemcpyDeviceToHost));
+    if (codebooks)
+        MK_HIP(hipMemcpy(codebooks, ix->books, sizeof(float) * (size_t)ix->M * 256 * ix->dsub,
+                         hipMemcpyDeviceToHost));
+    return MK_OK;
+}
+
+extern "C" mk_status mk_ivfpq_set_quantizers(mk_ivfpq* ix, const float* coarse,
+                                             const float* codebooks, mk_stream_t stream) {
+    MK_REQUIRE(ix && coarse && codebooks, MK_ERR_INVALID_ARG, "null pointer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    {
+        mk_status st = mk::alloc_quantizers(ix);
+        if (st != MK_OK) return st;
+    }
+    MK_HIP(hipMemcpyAsync(ix->coarse, coarse, sizeof(float) * (size_t)ix->nlist * ix->d,
+                          hipMemcpyHostToDevice, s));
+    MK_HIP(hipMemcpyAsync(ix->books, codebooks, sizeof(float) * (size_t)ix->M * 256 * ix->dsub,
+                          hipMemcpyHostToDevice, s));
+    mk_status st = mk::build_term1(ix, s);
+    if (st != MK_OK) return st;
+    mk::reset_lists(ix);
+    st = mk::upload_offsets(ix, s);
+    if (st != MK_OK) return st;
+    ix->trained = true;
+    return MK_OK;
+}
+
+extern "C" mk_status mk_ivfpq_get_lists(const mk_ivfpq* ix, int64_t* offsets, uint8_t* codes,
+                                        int64_t* ids) {
+    MK_REQUIRE(ix, MK_ERR_INVALID_ARG, "null index");
+    MK_HIP(hipDeviceSynchronize());
+    if (offsets) std::memcpy(offsets, ix->offsets.data(), sizeof(int64_t) * (ix->nlist + 1));
+    if (codes && ix->ntotal)
+        MK_HIP(hipMemcpy(codes, ix->codes, (size_t)ix->ntotal * ix->M, hipMemcpyDeviceToHost));
+    if (ids && ix->ntotal)
+        MK_HIP(hipMemcpy(ids, ix->ids, sizeof(int64_t) * ix->ntotal, hipMemcpyDeviceToHost));
+    return MK_OK;
 }

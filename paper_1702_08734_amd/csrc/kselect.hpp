@@ -1,7 +1,11 @@
 // Selector sizing shared by the kernels.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
+
+#include "mi_knn.h"
 
 namespace mk {
 
@@ -25,5 +29,17 @@ template <> struct SelParams<2> { static constexpr int T = 2; };
 template <> struct SelParams<4> { static constexpr int T = 4; };
 template <> struct SelParams<8> { static constexpr int T = 4; };
 template <> struct SelParams<16> { static constexpr int T = 8; };
+
+// Per row, select the k best of nseg sorted lists of k keys each
+// (partial[row][seg][k]) and write (score, index) pairs; sentinel keys become
+// (+inf, -1).  The second pass of the two-pass k-selection of Section 5.3.
+mk_status merge_key_lists(const uint64_t* partial, int64_t nrows, int32_t nseg, int32_t k,
+                          float* vals, int64_t* idx, hipStream_t s);
+
+// Exact k-NN (knn.hip); yn may be null (then computed) for L2.
+mk_status knn_search(const float* xq, int64_t nq, const float* xb, const float* yn, int64_t nb,
+                     int32_t d, int32_t k, mk_metric metric, float* D, int64_t* I,
+                     hipStream_t s);
+mk_status launch_norms(const float* x, int64_t n, int32_t d, float* out, hipStream_t s);
 
 }  // namespace mk
