@@ -122,8 +122,8 @@ mk_status mk_kmeans_assign(const float* x, int64_t n, int32_t d, const float* c,
  * c_b[t] becoming c_b[t] * (1 - s_t 2^-10), s_t = +1 for even t and -1 for
  * odd t (products in FP64, rounded to FP32); the empty cluster takes
  * floor(count_b / 2) of b's count.
- *   x [n, d], assign [n] int64 in [0, K), c [K, d] float32 in/out,
- *   counts [K] int64 out (may be NULL).
+ *   x [n, d], assign [n] int64 in [0, K) (points with other values are
+ *   ignored), c [K, d] float32 in/out, counts [K] int64 out (may be NULL).
  * Every step, the empty-cluster rule included, runs on the device.
  */
 mk_status mk_kmeans_update(const float* x, int64_t n, int32_t d, const int64_t* assign,

@@ -67,12 +67,13 @@ __global__ void gather_rows_kernel(const float* __restrict__ src, int32_t d,
 // Sum points into their centroid's FP64 accumulator (one thread per
 // coordinate, so neighbouring lanes add to neighbouring addresses).
 __global__ void km_accumulate(const float* __restrict__ x, int64_t n, int32_t d,
-                              const int64_t* __restrict__ assign, double* __restrict__ sums,
-                              unsigned long long* __restrict__ counts) {
+                              const int64_t* __restrict__ assign, int32_t K,
+                              double* __restrict__ sums, unsigned long long* __restrict__ counts) {
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (g >= n * d) return;
     const int64_t i = g / d, t = g % d;
     const int64_t a = assign[i];
+    if (a < 0 || a >= K) return;  // invalid assignments are ignored
     if (t == 0) atomicAdd(&counts[a], 1ull);
     atomicAdd(&sums[a * d + t], (double)x[g]);
 }
@@ -164,7 +165,7 @@ mk_status kmeans_update(const float* x, int64_t n, int32_t d, const int64_t* ass
     MK_HIP(hipMemsetAsync(cnt.ptr, 0, sizeof(unsigned long long) * (size_t)K, s));
     if (n > 0) {
         hipLaunchKernelGGL(km_accumulate, dim3((unsigned)ceil_div(n * d, kBlock)), dim3(kBlock), 0,
-                           s, x, n, d, assign, sums.as<double>(), cnt.as<unsigned long long>());
+                           s, x, n, d, assign, K, sums.as<double>(), cnt.as<unsigned long long>());
         MK_LAUNCHED();
     }
     hipLaunchKernelGGL(km_finalize, dim3((unsigned)ceil_div((int64_t)K * d, kBlock)), dim3(kBlock),
