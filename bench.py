@@ -9,7 +9,7 @@ direct-form re-rank).  The metric is TFLOP/s at 2 flop per multiply-add of
 the q.y term, 2 * nq * nb * d per search.
 
 Prints ONE JSON line.  Inputs are resident in device memory before timing
-starts.  `roofline` reports the dominant kernel (knn_tile_select) timed with
+starts.  `roofline` reports the dominant kernel (knn_fused) timed with
 HIP events inside the library over the timed steps; `cpu_baseline` times the
 float64 oracle on a bounded sample of the same queries on the host cores.
 """
@@ -25,7 +25,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 FP32_MFMA_PEAK_TFLOPS = 157.3
 KS = (1, 32, 256, 1024)
-PMC_FILE = os.path.join(ROOT, "profiles", "knn_tile_select_exact_large_pmc.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "knn_fused_exact_large_pmc.json")
 KERNEL_SOURCES = ["knn.hip", "wave_select.hpp", "kselect.hpp"]
 
 
@@ -122,7 +122,7 @@ def main() -> int:
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     api.profile_enable(False)
-    tile_ms, tile_n = api.profile_read("knn_tile_select")
+    tile_ms, tile_n = api.profile_read("knn_fused")
     merge_ms, merge_n = api.profile_read("knn_merge_rerank")
 
     flops_search = 2.0 * nq * nb * d
@@ -151,7 +151,7 @@ def main() -> int:
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "knn_tile_select",
+            "kernel": "knn_fused",
             "achieved": round(achieved, 3) if achieved else None,
             "peak": FP32_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",

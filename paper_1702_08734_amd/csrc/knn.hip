@@ -3,14 +3,15 @@
 // Layout of one call:
 //   1. norms: ||y||^2 per database row (one pass, Eq. 2), skipped for inner
 //      products or when the caller supplies them;
-//   2. knn_tile_select: the grid is (query block) x (database chunk).  A
-//      workgroup keeps its queries' MFMA A-operands in registers, streams its
-//      chunk in tiles, computes the q.y tile with v_mfma_f32_16x16x4f32,
-//      stages the tile through LDS, and every wave feeds the scores of its
-//      own queries (||y||^2 - 2 q.y for L2, -q.y for inner products; ||x||^2
-//      is constant per query and not needed to rank, Section 5.1) into
-//      register-resident selectors -- distance computation and k-selection in
-//      one kernel, so the distance matrix never reaches HBM;
+//   2. knn_fused: the grid is (query block) x (database chunk).  Producer
+//      waves keep their queries' MFMA A-operands in registers, stream the
+//      chunk in tiles of 64 rows (prefetching the next tile's rows into
+//      registers), compute the q.y tile with v_mfma_f32_16x16x4f32 and stage
+//      scores (||y||^2 - 2 q.y for L2, -q.y for inner products; ||x||^2 is
+//      constant per query and not needed to rank, Section 5.1) in LDS;
+//      consumer waves feed them to register-resident selectors -- distance
+//      computation and k-selection in one kernel, so the distance matrix
+//      never reaches HBM;
 //   3. knn_merge_rerank: one wave per query selects the best of the chunks'
 //      partial lists (the second pass of Section 5.3's two-pass selection),
 //      recomputes the kept candidates' distances in the direct form in FP32,
@@ -145,17 +146,6 @@ struct MultiSelect {
     }
 };
 
-// Kernel shape per queue size: queries per wave QW, waves NW.  The tile is
-// BQ = NW*QW queries by BN = 4096/BQ database rows, i.e. sixteen 16x16 MFMA
-// blocks, each wave owning NBW blocks of a single query block.
-template <int KR>
-struct TileShape;
-template <> struct TileShape<1> { static constexpr int QW = 8, NW = 8; };
-template <> struct TileShape<2> { static constexpr int QW = 8, NW = 4; };
-template <> struct TileShape<4> { static constexpr int QW = 4, NW = 4; };
-template <> struct TileShape<8> { static constexpr int QW = 2, NW = 8; };
-template <> struct TileShape<16> { static constexpr int QW = 2, NW = 8; };
-
 __device__ __forceinline__ float4 load4_guard(const float* __restrict__ row, int dim, int d,
                                               bool vec, bool ok) {
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -180,107 +170,175 @@ __device__ __forceinline__ int64_t xcd_logical_id(int64_t bid, int64_t nblocks) 
     return x * base + (x < rem ? x : rem) + pos;
 }
 
+// Workgroup of the fused kernel: 4 producer waves (one per SIMD) compute the
+// q.y tile of BQ queries x BN = 64 database rows per step with
+// v_mfma_f32_16x16x4f32 and write scores into one of two LDS slots, while 4
+// consumer waves (one per SIMD) run the selectors of the previous step's
+// tile from the other slot -- matrix cores and VALU selection overlap, one
+// barrier per step.  Each producer owns QPB query blocks x DPB database
+// blocks of 16 (a 4-producer grid of QG x DG), each consumer QW = BQ/NC
+// queries.  Sizes per wave-queue length KR and padded dimension DP:
+//   KR <= 2: BQ 64 (QW 16); KR = 4: BQ 32 (QW 8); KR >= 8 or DP > 128: BQ 16
+//   (QW 4, or QW 2 over 8 consumer waves for KR = 16).
+constexpr int kProducers = 4;
+
 template <int KR, int DP>
-__global__ __launch_bounds__(64 * TileShape<KR>::NW) void knn_tile_select(
+struct FusedShape {
+    // 1024-entry queues: 8 consumer waves of 2 queries (the state of four
+    // 1024-entry selectors does not fit one wave's registers)
+    static constexpr int NC = KR >= 16 ? 8 : 4;
+    // thread-queue length: 4 for 1024-entry queues so that two selectors and
+    // a working copy fit a consumer's registers
+    static constexpr int T = KR >= 16 ? 4 : SelParams<KR>::T;
+    static constexpr bool wide = DP > 128;
+    static constexpr int QPB = (!wide && KR <= 2) ? 2 : 1;
+    static constexpr int DPB = (!wide && KR <= 4) ? 2 : 1;
+    static constexpr int DG = DPB == 2 ? 2 : 4;
+    static constexpr int QG = kProducers / DG;
+    static constexpr int BQ = QG * QPB * 16;
+    static constexpr int BN = DG * DPB * 16;
+    static constexpr int QW = BQ / NC;
+    static_assert(BN == 64, "consumers take one column per lane");
+};
+
+template <int KR, int DP>
+__global__ __launch_bounds__(64 * (kProducers + FusedShape<KR, DP>::NC)) void knn_fused(
     const float* __restrict__ xq, int64_t nq, const float* __restrict__ xb,
     const float* __restrict__ yn, int64_t nb, int32_t d, int32_t vec, int32_t l2,
     int64_t chunk_len, int32_t nchunks, int32_t nqb, int32_t keff, uint64_t* __restrict__ part) {
-    constexpr int T = SelParams<KR>::T;
-    constexpr int QW = TileShape<KR>::QW;
-    constexpr int NW = TileShape<KR>::NW;
-    constexpr int BQ = NW * QW;
-    constexpr int QB = BQ / 16;
-    constexpr int BN = 4096 / BQ;
-    constexpr int DB = BN / 16;
-    constexpr int NBW = QB * DB / NW;
-    constexpr int NV = BN / 64;
+    using S = FusedShape<KR, DP>;
+    constexpr int T = S::T;
+    constexpr int BQ = S::BQ, BN = S::BN, QW = S::QW, QPB = S::QPB, DPB = S::DPB, DG = S::DG;
     constexpr int LDP = BN + 4;
     constexpr int S4 = DP / 16;
-    static_assert(QB * DB % NW == 0 && DB % NBW == 0, "tile shape");
+    constexpr int KS = 64 * KR;
 
-    __shared__ float dist[BQ * LDP];
+    __shared__ float scores[2][BQ * LDP];
 
     const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)nqb * nchunks);
     const int64_t chunk = logical / nqb;
     const int64_t qblk = logical % nqb;
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int li = lane & 15, lh = lane >> 4;
     const int64_t q0 = qblk * BQ;
     const int64_t c0 = chunk * chunk_len;
     const int64_t c1 = c0 + chunk_len < nb ? c0 + chunk_len : nb;
+    const int64_t nsteps = c1 > c0 ? (c1 - c0 + BN - 1) / BN : 0;
     const bool use_vec = vec != 0;
 
-    const int my_qb = (wave * NBW) / DB;
-    const int my_db0 = (wave * NBW) % DB;
-
-    // A operand: lane (i, h) holds query i's components 16*s + 4*h + e.
-    float4 areg[S4];
-    {
-        const int64_t q = q0 + my_qb * 16 + li;
-        const bool ok = q < nq;
-        const float* row = xq + (ok ? q : 0) * d;
+    if (wave < kProducers) {
+        // ------------------------------------------------ producer
+        const int li = lane & 15, lh = lane >> 4;
+        const int qg = wave / DG, dg = wave % DG;
+        // A operand: lane (i, h) holds query i's components 16*s + 4*h + e.
+        float4 areg[QPB][S4];
 #pragma unroll
-        for (int s = 0; s < S4; ++s) areg[s] = load4_guard(row, 16 * s + 4 * lh, d, use_vec, ok);
-    }
-
-    MultiSelect<KR, T, QW> sel;
-    sel.init(keff);
-
-    for (int64_t t0 = c0; t0 < c1; t0 += BN) {
-        floatx4 acc[NBW];
+        for (int qb = 0; qb < QPB; ++qb) {
+            const int64_t q = q0 + (qg * QPB + qb) * 16 + li;
+            const bool ok = q < nq;
+            const float* row = xq + (ok ? q : 0) * d;
 #pragma unroll
-        for (int j = 0; j < NBW; ++j) {
-            const int64_t yrow = t0 + (my_db0 + j) * 16 + li;
-            const bool ok = yrow < c1;
-            const float* row = xb + (ok ? yrow : 0) * d;
-            float4 b[S4];
+            for (int s4 = 0; s4 < S4; ++s4) areg[qb][s4] = load4_guard(row, 16 * s4 + 4 * lh, d, use_vec, ok);
+        }
+        float4 bc[DPB][S4];
+        float ync[DPB];
+        auto load_b = [&](int64_t t0, float4 (&b)[DPB][S4], float (&yv)[DPB]) {
 #pragma unroll
-            for (int s = 0; s < S4; ++s) b[s] = load4_guard(row, 16 * s + 4 * lh, d, use_vec, ok);
-            floatx4 c = {0.f, 0.f, 0.f, 0.f};
+            for (int db = 0; db < DPB; ++db) {
+                const int64_t yrow = t0 + (dg * DPB + db) * 16 + li;
+                const bool ok = yrow < c1;
+                const float* row = xb + (ok ? yrow : 0) * d;
 #pragma unroll
-            for (int s = 0; s < S4; ++s) {
-                c = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[s].x, b[s].x, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[s].y, b[s].y, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[s].z, b[s].z, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[s].w, b[s].w, c, 0, 0, 0);
+                for (int s4 = 0; s4 < S4; ++s4) b[db][s4] = load4_guard(row, 16 * s4 + 4 * lh, d, use_vec, ok);
+                yv[db] = (l2 && ok) ? yn[yrow] : 0.f;
             }
-            acc[j] = c;
-        }
-        // D[i][j] of a 16x16 block sits in lane j + 16*(i/4), element i%4.
+        };
+        if (nsteps > 0) load_b(c0, bc, ync);
+        for (int64_t s = 0; s <= nsteps; ++s) {
+            if (s < nsteps) {
+                const int64_t t0 = c0 + s * BN;
+                float4 bn[DPB][S4];
+                float ynn[DPB];
+                const bool more = s + 1 < nsteps;
+                if (more) load_b(t0 + BN, bn, ynn);
+                floatx4 acc[QPB][DPB];
 #pragma unroll
-        for (int j = 0; j < NBW; ++j) {
+                for (int qb = 0; qb < QPB; ++qb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                dist[(my_qb * 16 + 4 * lh + r) * LDP + (my_db0 + j) * 16 + li] = acc[j][r];
-        }
-        __syncthreads();
-#pragma unroll 1
-        for (int v = 0; v < NV; ++v) {
-            const int col = v * 64 + lane;
-            const int64_t g = t0 + col;
-            const bool ok = g < c1;
-            const float ynv = (l2 && ok) ? yn[g] : 0.f;
-            float score[QW];
+                    for (int db = 0; db < DPB; ++db) acc[qb][db] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int qq = 0; qq < QW; ++qq) {
-                const float c = dist[(wave * QW + qq) * LDP + col];
-                score[qq] = l2 ? fmaf(-2.f, c, ynv) : -c;
+                for (int s4 = 0; s4 < S4; ++s4) {
+#pragma unroll
+                    for (int qb = 0; qb < QPB; ++qb)
+#pragma unroll
+                        for (int db = 0; db < DPB; ++db)
+                            acc[qb][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[qb][s4].x, bc[db][s4].x, acc[qb][db], 0, 0, 0);
+#pragma unroll
+                    for (int qb = 0; qb < QPB; ++qb)
+#pragma unroll
+                        for (int db = 0; db < DPB; ++db)
+                            acc[qb][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[qb][s4].y, bc[db][s4].y, acc[qb][db], 0, 0, 0);
+#pragma unroll
+                    for (int qb = 0; qb < QPB; ++qb)
+#pragma unroll
+                        for (int db = 0; db < DPB; ++db)
+                            acc[qb][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[qb][s4].z, bc[db][s4].z, acc[qb][db], 0, 0, 0);
+#pragma unroll
+                    for (int qb = 0; qb < QPB; ++qb)
+#pragma unroll
+                        for (int db = 0; db < DPB; ++db)
+                            acc[qb][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[qb][s4].w, bc[db][s4].w, acc[qb][db], 0, 0, 0);
+                }
+                // D[i][j] of a 16x16 block sits in lane j + 16*(i/4), element i%4;
+                // the score is ||y||^2 - 2 q.y (L2) or -q.y (inner product).
+                float* slot = scores[s & 1];
+#pragma unroll
+                for (int qb = 0; qb < QPB; ++qb)
+#pragma unroll
+                    for (int db = 0; db < DPB; ++db)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float c = acc[qb][db][r];
+                            slot[((qg * QPB + qb) * 16 + 4 * lh + r) * LDP + (dg * DPB + db) * 16 + li] =
+                                l2 ? fmaf(-2.f, c, ync[db]) : -c;
+                        }
+                if (more) {
+#pragma unroll
+                    for (int db = 0; db < DPB; ++db) {
+                        ync[db] = ynn[db];
+#pragma unroll
+                        for (int s4 = 0; s4 < S4; ++s4) bc[db][s4] = bn[db][s4];
+                    }
+                }
             }
-            sel.offer(score, (uint32_t)g, ok);
+            __syncthreads();
         }
-        __syncthreads();
-    }
-    sel.finish();
-
-    constexpr int KS = 64 * KR;
+    } else {
+        // ------------------------------------------------ consumer
+        const int cw = wave - kProducers;
+        MultiSelect<KR, T, QW> sel;
+        sel.init(keff);
+        for (int64_t s = 0; s <= nsteps; ++s) {
+            if (s >= 1) {
+                const float* slot = scores[(s - 1) & 1];
+                const int64_t g = c0 + (s - 1) * BN + lane;
+                const bool ok = g < c1;
+                float score[QW];
 #pragma unroll
-    for (int qq = 0; qq < QW; ++qq) {
-        const int64_t q = q0 + wave * QW + qq;
-        if (q < nq) {
-            uint64_t* out = part + (q * nchunks + chunk) * KS;
+                for (int qq = 0; qq < QW; ++qq) score[qq] = slot[(cw * QW + qq) * LDP + lane];
+                sel.offer(score, (uint32_t)g, ok);
+            }
+            __syncthreads();
+        }
+        sel.finish();
 #pragma unroll
-            for (int r = 0; r < KR; ++r) out[r * 64 + lane] = sel.w[qq][r];
+        for (int qq = 0; qq < QW; ++qq) {
+            const int64_t q = q0 + cw * QW + qq;
+            if (q < nq) {
+                uint64_t* out = part + (q * nchunks + chunk) * KS;
+#pragma unroll
+                for (int r = 0; r < KR; ++r) out[r * 64 + lane] = sel.w[qq][r];
+            }
         }
     }
 }
@@ -385,10 +443,8 @@ template <int KR, int DP>
 mk_status knn_launch(const float* xq, int64_t nq, const float* xb, const float* yn, int64_t nb,
                      int32_t d, int32_t k, bool l2, bool vec, float* D, int64_t* I,
                      hipStream_t stream) {
-    constexpr int QW = TileShape<KR>::QW;
-    constexpr int NW = TileShape<KR>::NW;
-    constexpr int BQ = NW * QW;
-    constexpr int BN = 4096 / BQ;
+    constexpr int BQ = FusedShape<KR, DP>::BQ;
+    constexpr int BN = FusedShape<KR, DP>::BN;
     constexpr int KS = 64 * KR;
     const int keff = k + kSlack < KS ? k + kSlack : KS;
     const int64_t nqb = ceil_div(nq, BQ);
@@ -408,9 +464,9 @@ mk_status knn_launch(const float* xq, int64_t nq, const float* xb, const float* 
     const int64_t nblocks = nqb * nchunks;
     MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
     {
-        ProfScope prof("knn_tile_select", stream);
-        hipLaunchKernelGGL((knn_tile_select<KR, DP>), dim3((unsigned)nblocks), dim3(64 * NW), 0,
-                           stream, xq, nq, xb, yn, nb, d, (int32_t)vec, (int32_t)l2, chunk_len,
+        ProfScope prof("knn_fused", stream);
+        hipLaunchKernelGGL((knn_fused<KR, DP>), dim3((unsigned)nblocks),
+                           dim3(64 * (kProducers + FusedShape<KR, DP>::NC)), 0, stream, xq, nq, xb, yn, nb, d, (int32_t)vec, (int32_t)l2, chunk_len,
                            (int32_t)nchunks, (int32_t)nqb, keff, part.as<uint64_t>());
         MK_LAUNCHED();
     }
