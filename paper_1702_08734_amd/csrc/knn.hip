@@ -201,10 +201,14 @@ struct FusedShape {
     static_assert(BN == 64, "consumers take one column per lane");
 };
 
-template <int KR, int DP>
-__global__ __launch_bounds__(64 * (kProducers + FusedShape<KR, DP>::NC)) void knn_fused(
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef __attribute__((address_space(1))) void* gbl_ptr_t;
+
+template <int KR, int DP, bool VEC, bool L2>
+__global__ __launch_bounds__(64 * (kProducers + FusedShape<KR, DP>::NC))
+__attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(
     const float* __restrict__ xq, int64_t nq, const float* __restrict__ xb,
-    const float* __restrict__ yn, int64_t nb, int32_t d, int32_t vec, int32_t l2,
+    const float* __restrict__ yn, int64_t nb, int32_t d,
     int64_t chunk_len, int32_t nchunks, int32_t nqb, int32_t keff, uint64_t* __restrict__ part) {
     using S = FusedShape<KR, DP>;
     constexpr int T = S::T;
@@ -212,7 +216,14 @@ __global__ __launch_bounds__(64 * (kProducers + FusedShape<KR, DP>::NC)) void kn
     constexpr int LDP = BN + 4;
     constexpr int S4 = DP / 16;
     constexpr int KS = 64 * KR;
+    // Database tile in LDS: BN rows of DP floats as 16-byte granules, GR per
+    // row; granule c of row j is stored at position c ^ (j & SW) so that the
+    // 16 rows read by one MFMA operand load fall in different banks.
+    constexpr int GR = DP / 4;
+    constexpr int SW = (GR % 16 == 0) ? 15 : 7;
+    constexpr int NI = BN * GR / 64;  // 64-lane granule loads per tile
 
+    __shared__ __align__(16) float btile[2][BN * DP];
     __shared__ float scores[2][BQ * LDP];
 
     const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)nqb * nchunks);
@@ -224,7 +235,33 @@ __global__ __launch_bounds__(64 * (kProducers + FusedShape<KR, DP>::NC)) void kn
     const int64_t c0 = chunk * chunk_len;
     const int64_t c1 = c0 + chunk_len < nb ? c0 + chunk_len : nb;
     const int64_t nsteps = c1 > c0 ? (c1 - c0 + BN - 1) / BN : 0;
-    const bool use_vec = vec != 0;
+
+    // Load the tile of rows [t0, t0 + BN) into btile[buf]; producers share
+    // the NI granule loads.  Rows past the chunk repeat its last row and
+    // granules past d repeat granule 0: both only ever meet zero A
+    // components or unconsumed score columns.
+    auto load_tile = [&](int64_t t0, int buf) {
+        for (int i = wave; i < NI; i += kProducers) {
+            const int g = i * 64 + lane;
+            const int j = g / GR;
+            const int c = (g % GR) ^ (j & SW);
+            int64_t row = t0 + j;
+            row = row < c1 ? row : c1 - 1;
+            const int col = 4 * c < d ? 4 * c : 0;
+            const float* src = xb + row * d + col;
+            float* dst = &btile[buf][i * 256];  // 64 lanes x 4 floats
+            if constexpr (VEC) {
+                __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)dst, 16, 0, 0);
+            } else {
+                float4 v;
+                v.x = col + 0 < d ? src[0] : 0.f;
+                v.y = col + 1 < d ? src[1] : 0.f;
+                v.z = col + 2 < d ? src[2] : 0.f;
+                v.w = col + 3 < d ? src[3] : 0.f;
+                *reinterpret_cast<float4*>(dst + lane * 4) = v;
+            }
+        }
+    };
 
     if (wave < kProducers) {
         // ------------------------------------------------ producer
@@ -238,29 +275,15 @@ __global__ __launch_bounds__(64 * (kProducers + FusedShape<KR, DP>::NC)) void kn
             const bool ok = q < nq;
             const float* row = xq + (ok ? q : 0) * d;
 #pragma unroll
-            for (int s4 = 0; s4 < S4; ++s4) areg[qb][s4] = load4_guard(row, 16 * s4 + 4 * lh, d, use_vec, ok);
+            for (int s4 = 0; s4 < S4; ++s4) areg[qb][s4] = load4_guard(row, 16 * s4 + 4 * lh, d, VEC, ok);
         }
-        float4 bc[DPB][S4];
-        float ync[DPB];
-        auto load_b = [&](int64_t t0, float4 (&b)[DPB][S4], float (&yv)[DPB]) {
-#pragma unroll
-            for (int db = 0; db < DPB; ++db) {
-                const int64_t yrow = t0 + (dg * DPB + db) * 16 + li;
-                const bool ok = yrow < c1;
-                const float* row = xb + (ok ? yrow : 0) * d;
-#pragma unroll
-                for (int s4 = 0; s4 < S4; ++s4) b[db][s4] = load4_guard(row, 16 * s4 + 4 * lh, d, use_vec, ok);
-                yv[db] = (l2 && ok) ? yn[yrow] : 0.f;
-            }
-        };
-        if (nsteps > 0) load_b(c0, bc, ync);
+        if (nsteps > 0) load_tile(c0, 0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
         for (int64_t s = 0; s <= nsteps; ++s) {
             if (s < nsteps) {
-                const int64_t t0 = c0 + s * BN;
-                float4 bn[DPB][S4];
-                float ynn[DPB];
-                const bool more = s + 1 < nsteps;
-                if (more) load_b(t0 + BN, bn, ynn);
+                if (s + 1 < nsteps) load_tile(c0 + (s + 1) * BN, (int)((s + 1) & 1));
+                const float* bt = btile[s & 1];
                 floatx4 acc[QPB][DPB];
 #pragma unroll
                 for (int qb = 0; qb < QPB; ++qb)
@@ -268,64 +291,60 @@ __global__ __launch_bounds__(64 * (kProducers + FusedShape<KR, DP>::NC)) void kn
                     for (int db = 0; db < DPB; ++db) acc[qb][db] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int s4 = 0; s4 < S4; ++s4) {
+                    float4 b[DPB];
+#pragma unroll
+                    for (int db = 0; db < DPB; ++db) {
+                        const int j = (dg * DPB + db) * 16 + li;
+                        const int c = (4 * s4 + lh) ^ (j & SW);
+                        b[db] = *reinterpret_cast<const float4*>(bt + (j * GR + c) * 4);
+                    }
 #pragma unroll
                     for (int qb = 0; qb < QPB; ++qb)
 #pragma unroll
-                        for (int db = 0; db < DPB; ++db)
-                            acc[qb][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[qb][s4].x, bc[db][s4].x, acc[qb][db], 0, 0, 0);
-#pragma unroll
-                    for (int qb = 0; qb < QPB; ++qb)
-#pragma unroll
-                        for (int db = 0; db < DPB; ++db)
-                            acc[qb][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[qb][s4].y, bc[db][s4].y, acc[qb][db], 0, 0, 0);
-#pragma unroll
-                    for (int qb = 0; qb < QPB; ++qb)
-#pragma unroll
-                        for (int db = 0; db < DPB; ++db)
-                            acc[qb][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[qb][s4].z, bc[db][s4].z, acc[qb][db], 0, 0, 0);
-#pragma unroll
-                    for (int qb = 0; qb < QPB; ++qb)
-#pragma unroll
-                        for (int db = 0; db < DPB; ++db)
-                            acc[qb][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[qb][s4].w, bc[db][s4].w, acc[qb][db], 0, 0, 0);
+                        for (int db = 0; db < DPB; ++db) {
+                            acc[qb][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[qb][s4].x, b[db].x, acc[qb][db], 0, 0, 0);
+                            acc[qb][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[qb][s4].y, b[db].y, acc[qb][db], 0, 0, 0);
+                            acc[qb][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[qb][s4].z, b[db].z, acc[qb][db], 0, 0, 0);
+                            acc[qb][db] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[qb][s4].w, b[db].w, acc[qb][db], 0, 0, 0);
+                        }
                 }
-                // D[i][j] of a 16x16 block sits in lane j + 16*(i/4), element i%4;
-                // the score is ||y||^2 - 2 q.y (L2) or -q.y (inner product).
+                // D[i][j] of a 16x16 block sits in lane j + 16*(i/4), element i%4.
                 float* slot = scores[s & 1];
 #pragma unroll
                 for (int qb = 0; qb < QPB; ++qb)
 #pragma unroll
                     for (int db = 0; db < DPB; ++db)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const float c = acc[qb][db][r];
+                        for (int r = 0; r < 4; ++r)
                             slot[((qg * QPB + qb) * 16 + 4 * lh + r) * LDP + (dg * DPB + db) * 16 + li] =
-                                l2 ? fmaf(-2.f, c, ync[db]) : -c;
-                        }
-                if (more) {
-#pragma unroll
-                    for (int db = 0; db < DPB; ++db) {
-                        ync[db] = ynn[db];
-#pragma unroll
-                        for (int s4 = 0; s4 < S4; ++s4) bc[db][s4] = bn[db][s4];
-                    }
-                }
+                                acc[qb][db][r];
+                __builtin_amdgcn_s_waitcnt(0);
             }
             __syncthreads();
         }
     } else {
         // ------------------------------------------------ consumer
+        // score = ||y||^2 - 2 q.y (L2) or -q.y (inner product); ||x||^2 is the
+        // same for every candidate of a query and does not change its rank.
         const int cw = wave - kProducers;
         MultiSelect<KR, T, QW> sel;
         sel.init(keff);
+        __syncthreads();
+        float ynext = 0.f;
+        if (L2 && c0 + lane < c1) ynext = yn[c0 + lane];
         for (int64_t s = 0; s <= nsteps; ++s) {
             if (s >= 1) {
                 const float* slot = scores[(s - 1) & 1];
                 const int64_t g = c0 + (s - 1) * BN + lane;
                 const bool ok = g < c1;
+                const float ynv = ynext;
+                if (L2 && g + BN < c1) ynext = yn[g + BN];
                 float score[QW];
 #pragma unroll
-                for (int qq = 0; qq < QW; ++qq) score[qq] = slot[(cw * QW + qq) * LDP + lane];
+                for (int qq = 0; qq < QW; ++qq) {
+                    const float c = slot[(cw * QW + qq) * LDP + lane];
+                    score[qq] = L2 ? fmaf(-2.f, c, ynv) : -c;
+                }
                 sel.offer(score, (uint32_t)g, ok);
             }
             __syncthreads();
@@ -465,8 +484,11 @@ mk_status knn_launch(const float* xq, int64_t nq, const float* xb, const float* 
     MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
     {
         ProfScope prof("knn_fused", stream);
-        hipLaunchKernelGGL((knn_fused<KR, DP>), dim3((unsigned)nblocks),
-                           dim3(64 * (kProducers + FusedShape<KR, DP>::NC)), 0, stream, xq, nq, xb, yn, nb, d, (int32_t)vec, (int32_t)l2, chunk_len,
+        auto kern = vec ? (l2 ? knn_fused<KR, DP, true, true> : knn_fused<KR, DP, true, false>)
+                        : (l2 ? knn_fused<KR, DP, false, true> : knn_fused<KR, DP, false, false>);
+        hipLaunchKernelGGL(kern, dim3((unsigned)nblocks),
+                           dim3(64 * (kProducers + FusedShape<KR, DP>::NC)), 0, stream, xq, nq,
+                           xb, yn, nb, d, chunk_len,
                            (int32_t)nchunks, (int32_t)nqb, keff, part.as<uint64_t>());
         MK_LAUNCHED();
     }
