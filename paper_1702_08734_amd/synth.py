@@ -101,14 +101,11 @@ def choose_rows(n: int, count: int, seed: int) -> np.ndarray:
     return rng.permutation(n)[:count].astype(np.int64)
 
 
-# Seeds of the five workloads (base + offset: +0 database, +1 queries,
-# +2 training-sample choice, +3 coarse k-means init, +4+m PQ init,
-# +20 learned-nprobe training queries, +21 network init, +22 arrivals).
-SEED = {"exact_small": 101, "exact_large": 102, "ivfpq": 103, "mixed": 104, "learned": 105}
-
-
-def pq_init_rows(n: int, M: int, seed: int) -> np.ndarray:
-    """[M, 256] Forgy rows for the M sub-quantizers (seed + m each)."""
+def pq_init_rows(n: int, M: int, seed) -> np.ndarray:
+    """[M, 256] Forgy rows for the M sub-quantizers: sub-quantizer m draws
+    with seed + m (integer seed) or entropy (*seed, m) (tuple seed)."""
+    if isinstance(seed, tuple):
+        return np.stack([choose_rows(n, 256, (*seed, m)) for m in range(M)])
     return np.stack([choose_rows(n, 256, seed + m) for m in range(M)])
 
 
@@ -129,3 +126,17 @@ def exact_large(nb: int = 1_000_000, nq: int = 10_000):
 def kselect_rows(nrows: int = 10_000, length: int = 128_000):
     """Row-wise k-selection input: U[0, 1) float32 rows."""
     return uniform_rows(nrows, length, (106, 0))
+
+
+def ivfpq_workload(nb: int = 10_000_000, nq: int = 10_000, nt: int = 500_000):
+    """IVFADC workload: database and queries from a 1,000-component mixture in
+    d = 128, a training sample of nt database rows drawn without replacement,
+    Forgy rows for 4,096 coarse centroids and 16 sub-quantizers."""
+    mix = Mixture(1000, 128, (103, 99))
+    xb = mix.sample(nb, (103, 0))
+    xq = mix.sample(nq, (103, 1))
+    sample = choose_rows(nb, nt, (103, 2))
+    return {"xb": xb, "xq": xq, "sample": sample, "nlist": 4096, "M": 16,
+            "coarse_init": choose_rows(nt, 4096, (103, 3)),
+            "pq_init": pq_init_rows(nt, 16, (103, 4)), "k": 100,
+            "nprobes": (1, 8, 32, 128)}
