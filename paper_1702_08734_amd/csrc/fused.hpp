@@ -1,0 +1,494 @@
+// Fused exact-search kernel shared by the FP32, BF16 and FP8 paths: MFMA
+// distance tiles computed by producer waves feed register-resident selectors
+// in consumer waves through LDS (Section 5.1 layout with the k-selection of
+// Section 4.2 fused into the distance kernel), plus the second-pass merge and
+// direct-form FP32 re-rank of the kept candidates.
+#pragma once
+
+#include "common.hpp"
+#include "kselect.hpp"
+#include "profile.hpp"
+#include "wave_select.hpp"
+
+namespace mk {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef __attribute__((address_space(1))) void* gbl_ptr_t;
+
+// ---------------------------------------------------------------- selectors
+// QW independent selectors held by one wave (one per query the wave owns).
+// Merges run one query at a time through a working copy so that the merge
+// network is emitted once, not once per query.
+template <int KR, int T, int QW>
+struct MultiSelect {
+    uint64_t w[QW][KR];
+    uint64_t tq[QW][T];
+    uint64_t kth[QW];
+    float kth_f[QW];
+    int keff;
+
+    __device__ __forceinline__ void init(int k_eff) {
+        keff = k_eff;
+#pragma unroll
+        for (int q = 0; q < QW; ++q) {
+#pragma unroll
+            for (int r = 0; r < KR; ++r) w[q][r] = kSentinel;
+#pragma unroll
+            for (int i = 0; i < T; ++i) tq[q][i] = kSentinel;
+            kth[q] = kSentinel;
+            kth_f[q] = INFINITY;
+        }
+    }
+
+    __device__ __forceinline__ void merge_slot(int q) {
+        uint64_t ww[KR], tt[T];
+#pragma unroll
+        for (int r = 0; r < KR; ++r) ww[r] = opaque(w[0][r]);
+#pragma unroll
+        for (int i = 0; i < T; ++i) tt[i] = opaque(tq[0][i]);
+#pragma unroll
+        for (int qq = 1; qq < QW; ++qq) {
+            const bool hit = qq == q;
+#pragma unroll
+            for (int r = 0; r < KR; ++r) {
+                const uint64_t e = opaque(w[qq][r]);
+                ww[r] = hit ? e : ww[r];
+            }
+#pragma unroll
+            for (int i = 0; i < T; ++i) {
+                const uint64_t e = opaque(tq[qq][i]);
+                tt[i] = hit ? e : tt[i];
+            }
+        }
+        ws_merge<KR, T>(ww, tt);
+        const uint64_t kk = ws_element<KR>(ww, keff - 1);
+        const float kf = kk == kSentinel ? INFINITY : key_score(kk);
+#pragma unroll
+        for (int qq = 0; qq < QW; ++qq) {
+            const bool hit = qq == q;
+#pragma unroll
+            for (int r = 0; r < KR; ++r) w[qq][r] = hit ? opaque(ww[r]) : w[qq][r];
+#pragma unroll
+            for (int i = 0; i < T; ++i) tq[qq][i] = hit ? kSentinel : tq[qq][i];
+            kth[qq] = hit ? kk : kth[qq];
+            kth_f[qq] = hit ? kf : kth_f[qq];
+        }
+    }
+
+    // Offer, for every query q, this lane's candidate (score[q], idx); ok
+    // false means no candidate.  A query whose scores all lose to its current
+    // k-th score is skipped after one compare per lane.
+    __device__ __forceinline__ void offer(const float (&score)[QW], uint32_t idx, bool ok) {
+        uint32_t full = 0;
+#pragma unroll
+        for (int q = 0; q < QW; ++q) {
+            if (__any(ok && score[q] <= kth_f[q])) {
+                const uint64_t key = ok ? make_key(score[q], idx) : kSentinel;
+                const bool take = key < kth[q];
+                if (__any(take)) {
+                    tq_push<T>(tq[q], key, take);
+                    if (__any(tq_full<T>(tq[q]))) full |= 1u << q;
+                }
+            }
+        }
+        while (full) {
+            const int q = __builtin_ctz(full);
+            full &= full - 1;
+            merge_slot(q);
+        }
+    }
+
+    __device__ __forceinline__ void finish() {
+#pragma unroll 1
+        for (int q = 0; q < QW; ++q) merge_slot(q);
+    }
+};
+
+// ---------------------------------------------------------------- operands
+// Operand formats of the distance tile.  A 16-byte granule holds EPG
+// elements; lane (i, h) of a 16x16 MFMA block supplies granule 4*s + h of
+// its query (A) or database row (B) at granule step s, so both operands use
+// the same component order and the sum over components is exact-order
+// independent of it.
+struct OpF32 {   // v_mfma_f32_16x16x4f32, four per granule
+    static constexpr int EPG = 4;
+    static constexpr int BYTES = 4;
+    static constexpr bool SCALED = false;
+    __device__ static __forceinline__ floatx4 mma(floatx4 c, uint4 a, uint4 b) {
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+        return c;
+    }
+};
+struct OpBF16 {  // v_mfma_f32_16x16x32_bf16, one per granule
+    static constexpr int EPG = 8;
+    static constexpr int BYTES = 2;
+    static constexpr bool SCALED = false;
+    __device__ static __forceinline__ floatx4 mma(floatx4 c, uint4 a, uint4 b) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    }
+};
+struct OpFP8 {   // v_mfma_f32_16x16x32_fp8_fp8 (OCP E4M3), two per granule
+    static constexpr int EPG = 16;
+    static constexpr int BYTES = 1;
+    static constexpr bool SCALED = true;
+    __device__ static __forceinline__ floatx4 mma(floatx4 c, uint4 a, uint4 b) {
+        const long a0 = (long)(((uint64_t)a.y << 32) | a.x), a1 = (long)(((uint64_t)a.w << 32) | a.z);
+        const long b0 = (long)(((uint64_t)b.y << 32) | b.x), b1 = (long)(((uint64_t)b.w << 32) | b.z);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, c, 0, 0, 0);
+        return c;
+    }
+};
+
+// Granule c (16 bytes) of a row with `stride` elements of which the first
+// `valid` are real; granules past `valid` read as zero.  Rows whose length in
+// bytes is not a multiple of 16 take the element-wise path (FP32 only).
+template <class Op, bool VEC>
+__device__ __forceinline__ uint4 load_granule(const void* row_base, int c, int valid, bool ok) {
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (!ok) return v;
+    const int e0 = c * Op::EPG;
+    if constexpr (VEC) {
+        if (e0 < valid)
+            v = *reinterpret_cast<const uint4*>(static_cast<const unsigned char*>(row_base) + (size_t)e0 * Op::BYTES);
+    } else {
+        static_assert(Op::BYTES == 4, "element-wise path is FP32 only");
+        const float* r = static_cast<const float*>(row_base);
+        if (e0 < valid) v.x = __float_as_uint(r[e0]);
+        if (e0 + 1 < valid) v.y = __float_as_uint(r[e0 + 1]);
+        if (e0 + 2 < valid) v.z = __float_as_uint(r[e0 + 2]);
+        if (e0 + 3 < valid) v.w = __float_as_uint(r[e0 + 3]);
+    }
+    return v;
+}
+
+// Map hardware workgroup ids (dispatched round-robin over the 8 XCDs) to
+// logical ids so that each XCD runs a contiguous logical range: the
+// workgroups sharing an XCD's L2 then walk the same database chunk.
+__device__ __forceinline__ int64_t xcd_logical_id(int64_t bid, int64_t nblocks) {
+    const int64_t x = bid & 7, pos = bid >> 3;
+    const int64_t base = nblocks >> 3, rem = nblocks & 7;
+    return x * base + (x < rem ? x : rem) + pos;
+}
+
+// Workgroup of the fused kernel: 4 producer waves (one per SIMD) compute the
+// q.y tile of BQ queries x BN = 64 database rows per step on the matrix
+// cores and write it to one of two LDS slots, while consumer waves run the
+// selectors of the previous step's tile from the other slot -- MFMA and VALU
+// selection overlap, one barrier per step.  Each producer owns QPB query
+// blocks x DPB database blocks of 16 (a 4-producer grid of QG x DG), each
+// consumer QW = BQ/NC queries.  Sizes per wave-queue length KR and padded row
+// bytes RB: KR <= 2: BQ 64 (QW 16); KR = 4: BQ 32 (QW 8); KR >= 8 or rows
+// over 512 bytes: BQ 16 (QW 4, or QW 2 over 8 consumer waves for KR = 16).
+constexpr int kProducers = 4;
+
+template <int KR, int RB>
+struct FusedShape {
+    static constexpr int NC = KR >= 16 ? 8 : 4;
+    // thread-queue length: 4 for 1024-entry queues so that two selectors and
+    // a working copy fit a consumer's registers
+    static constexpr int T = KR >= 16 ? 4 : SelParams<KR>::T;
+    static constexpr bool wide = RB > 512;
+    static constexpr int QPB = (!wide && KR <= 2) ? 2 : 1;
+    static constexpr int DPB = (!wide && KR <= 4) ? 2 : 1;
+    static constexpr int DG = DPB == 2 ? 2 : 4;
+    static constexpr int QG = kProducers / DG;
+    static constexpr int BQ = QG * QPB * 16;
+    static constexpr int BN = DG * DPB * 16;
+    static constexpr int QW = BQ / NC;
+    static_assert(BN == 64, "consumers take one column per lane");
+};
+
+// Per-call arguments of the fused kernel.
+struct FusedArgs {
+    const void* xq;       // queries, `stride` elements per row
+    const void* xb;       // database rows, same format
+    const float* yn;      // ||y||^2 per row (L2 only)
+    const float* qinv;    // per-query 1/scale (scaled formats only)
+    const float* yinv;    // per-row 1/scale (scaled formats only)
+    int64_t nq, nb;
+    int32_t stride;       // elements per row in memory
+    int32_t valid;        // leading elements per row that are real (rest zero)
+    int64_t chunk_len;
+    int32_t nchunks, nqb, keff;
+    uint64_t* part;       // [nq][nchunks][64 * KR] keys
+};
+
+template <class Op, int KR, int DP, bool VEC, bool L2>
+__global__ __launch_bounds__(64 * (kProducers + FusedShape<KR, DP * Op::BYTES>::NC))
+__attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
+    using S = FusedShape<KR, DP * Op::BYTES>;
+    constexpr int T = S::T;
+    constexpr int BQ = S::BQ, BN = S::BN, QW = S::QW, QPB = S::QPB, DPB = S::DPB, DG = S::DG;
+    constexpr int LDP = BN + 4;
+    constexpr int KS = 64 * KR;
+    // Database tile in LDS: BN rows of GR 16-byte granules; granule c of row j
+    // is stored at position c ^ (j & SW) so that the 16 rows read by one MFMA
+    // operand load fall in different banks.
+    constexpr int GR = DP / Op::EPG;
+    constexpr int S4 = GR / 4;  // granule steps per row
+    static_assert(GR % 4 == 0, "padded row must be a multiple of 4 granules");
+    constexpr int SW = (GR % 16 == 0) ? 15 : (GR % 8 == 0) ? 7 : 3;
+    constexpr int NI = BN * GR / 64;  // 64-lane granule loads per tile
+
+    __shared__ __align__(16) uint4 btile[2][BN * GR];
+    __shared__ float scores[2][BQ * LDP];
+
+    const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)args.nqb * args.nchunks);
+    const int64_t chunk = logical / args.nqb;
+    const int64_t qblk = logical % args.nqb;
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int64_t q0 = qblk * BQ;
+    const int64_t c0 = chunk * args.chunk_len;
+    const int64_t c1 = c0 + args.chunk_len < args.nb ? c0 + args.chunk_len : args.nb;
+    const int64_t nsteps = c1 > c0 ? (c1 - c0 + BN - 1) / BN : 0;
+    const int64_t row_bytes = (int64_t)args.stride * Op::BYTES;
+    const unsigned char* xb = static_cast<const unsigned char*>(args.xb);
+
+    // Load the tile of rows [t0, t0 + BN) into btile[buf]; producers share
+    // the NI granule loads.  Rows past the chunk repeat its last row and
+    // granules past the valid elements repeat granule 0: both only ever meet
+    // zero A components or unconsumed score columns.
+    auto load_tile = [&](int64_t t0, int buf) {
+        for (int i = wave; i < NI; i += kProducers) {
+            const int g = i * 64 + lane;
+            const int j = g / GR;
+            const int c = (g % GR) ^ (j & SW);
+            int64_t row = t0 + j;
+            row = row < c1 ? row : c1 - 1;
+            const int cc = c * Op::EPG < args.valid ? c : 0;
+            const unsigned char* src = xb + row * row_bytes + (int64_t)cc * 16;
+            uint4* dst = &btile[buf][i * 64];
+            if constexpr (VEC) {
+                __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)dst, 16, 0, 0);
+            } else {
+                dst[lane] = load_granule<Op, false>(xb + row * row_bytes, cc, args.valid, true);
+            }
+        }
+    };
+
+    if (wave < kProducers) {
+        // ------------------------------------------------ producer
+        const int li = lane & 15, lh = lane >> 4;
+        const int qg = wave / DG, dg = wave % DG;
+        const unsigned char* xq = static_cast<const unsigned char*>(args.xq);
+        uint4 areg[QPB][S4];
+#pragma unroll
+        for (int qb = 0; qb < QPB; ++qb) {
+            const int64_t q = q0 + (qg * QPB + qb) * 16 + li;
+            const bool ok = q < args.nq;
+            const unsigned char* row = xq + (ok ? q : 0) * row_bytes;
+#pragma unroll
+            for (int s4 = 0; s4 < S4; ++s4) areg[qb][s4] = load_granule<Op, VEC>(row, 4 * s4 + lh, args.valid, ok);
+        }
+        if (nsteps > 0) load_tile(c0, 0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        for (int64_t s = 0; s <= nsteps; ++s) {
+            if (s < nsteps) {
+                if (s + 1 < nsteps) load_tile(c0 + (s + 1) * BN, (int)((s + 1) & 1));
+                const uint4* bt = btile[s & 1];
+                floatx4 acc[QPB][DPB];
+#pragma unroll
+                for (int qb = 0; qb < QPB; ++qb)
+#pragma unroll
+                    for (int db = 0; db < DPB; ++db) acc[qb][db] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s4 = 0; s4 < S4; ++s4) {
+                    uint4 b[DPB];
+#pragma unroll
+                    for (int db = 0; db < DPB; ++db) {
+                        const int j = (dg * DPB + db) * 16 + li;
+                        b[db] = bt[j * GR + ((4 * s4 + lh) ^ (j & SW))];
+                    }
+#pragma unroll
+                    for (int qb = 0; qb < QPB; ++qb)
+#pragma unroll
+                        for (int db = 0; db < DPB; ++db) acc[qb][db] = Op::mma(acc[qb][db], areg[qb][s4], b[db]);
+                }
+                // D[i][j] of a 16x16 block sits in lane j + 16*(i/4), element i%4.
+                float* slot = scores[s & 1];
+#pragma unroll
+                for (int qb = 0; qb < QPB; ++qb)
+#pragma unroll
+                    for (int db = 0; db < DPB; ++db)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            slot[((qg * QPB + qb) * 16 + 4 * lh + r) * LDP + (dg * DPB + db) * 16 + li] =
+                                acc[qb][db][r];
+                __builtin_amdgcn_s_waitcnt(0);
+            }
+            __syncthreads();
+        }
+    } else {
+        // ------------------------------------------------ consumer
+        // score = ||y||^2 - 2 q.y (L2) or -q.y (inner product); ||x||^2 is the
+        // same for every candidate of a query and does not change its rank.
+        // Scaled formats multiply q.y by the query's and the row's 1/scale.
+        const int cw = wave - kProducers;
+        MultiSelect<KR, T, QW> sel;
+        sel.init(args.keff);
+        float qs[QW];
+#pragma unroll
+        for (int qq = 0; qq < QW; ++qq) {
+            const int64_t q = q0 + cw * QW + qq;
+            qs[qq] = (Op::SCALED && q < args.nq) ? args.qinv[q] : 1.f;
+        }
+        __syncthreads();
+        float ynext = 0.f, ysnext = 1.f;
+        if (c0 + lane < c1) {
+            if (L2) ynext = args.yn[c0 + lane];
+            if (Op::SCALED) ysnext = args.yinv[c0 + lane];
+        }
+        for (int64_t s = 0; s <= nsteps; ++s) {
+            if (s >= 1) {
+                const float* slot = scores[(s - 1) & 1];
+                const int64_t g = c0 + (s - 1) * BN + lane;
+                const bool ok = g < c1;
+                const float ynv = ynext, ysv = ysnext;
+                if (g + BN < c1) {
+                    if (L2) ynext = args.yn[g + BN];
+                    if (Op::SCALED) ysnext = args.yinv[g + BN];
+                }
+                float score[QW];
+#pragma unroll
+                for (int qq = 0; qq < QW; ++qq) {
+                    float c = slot[(cw * QW + qq) * LDP + lane];
+                    if (Op::SCALED) c = c * qs[qq] * ysv;
+                    score[qq] = L2 ? fmaf(-2.f, c, ynv) : -c;
+                }
+                sel.offer(score, (uint32_t)g, ok);
+            }
+            __syncthreads();
+        }
+        sel.finish();
+#pragma unroll
+        for (int qq = 0; qq < QW; ++qq) {
+            const int64_t q = q0 + cw * QW + qq;
+            if (q < args.nq) {
+                uint64_t* out = args.part + (q * args.nchunks + chunk) * KS;
+#pragma unroll
+                for (int r = 0; r < KR; ++r) out[r * 64 + lane] = sel.w[qq][r];
+            }
+        }
+    }
+}
+
+// Chunking of the database: enough workgroups to fill the chip several times
+// over, chunks long enough (>= 32 queue lengths) that partial lists stay small.
+inline void plan_chunks(int64_t nq, int64_t nb, int BQ, int BN, int KS, int64_t* nqb,
+                        int64_t* nchunks, int64_t* chunk_len) {
+    *nqb = ceil_div(nq, BQ);
+    int64_t want = ceil_div(4096, *nqb);
+    int64_t max_by_len = nb / (32 * KS) > 1 ? nb / (32 * KS) : 1;
+    int64_t nc = want < max_by_len ? want : max_by_len;
+    if (nc < 1) nc = 1;
+    int64_t cl = ceil_div(ceil_div(nb, nc), BN) * BN;
+    if (cl == 0) cl = BN;
+    *chunk_len = cl;
+    *nchunks = nb > 0 ? ceil_div(nb, cl) : 1;
+}
+
+constexpr int kMergeWaves = 4;
+constexpr int kMaxDim = 512;
+
+template <int KR>
+__global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
+    const uint64_t* __restrict__ part, int32_t nchunks, const float* __restrict__ xq, int64_t nq,
+    const float* __restrict__ xb, int32_t d, int32_t vec, int32_t l2, int32_t k, int32_t keff,
+    float* __restrict__ D, int64_t* __restrict__ I) {
+    constexpr int T = SelParams<KR>::T;
+    constexpr int KS = 64 * KR;
+    __shared__ __align__(16) float xs[kMergeWaves][kMaxDim];
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int64_t q = (int64_t)blockIdx.x * kMergeWaves + wave;
+    if (q >= nq) return;
+
+    WaveSelect<KR, T> ws;
+    ws.init(keff);
+    const uint64_t* p = part + q * nchunks * KS;
+    // Each chunk's list is sorted; only its first keff entries can survive.
+    const int per = (keff + 63) & ~63;
+#pragma unroll 1
+    for (int c = 0; c < nchunks; ++c) {
+#pragma unroll 1
+        for (int e = 0; e < per; e += 64) {
+            const int i = e + lane;
+            if (ws.push(i < keff ? p[(int64_t)c * KS + i] : kSentinel)) ws.merge();
+        }
+    }
+    ws.finish();
+
+    const float* x = xq + q * d;
+    for (int t = lane; t < d; t += 64) xs[wave][t] = x[t];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+
+    uint64_t nk[KR];
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const uint64_t key = ws.w[r];
+        const int e = r * 64 + lane;
+        nk[r] = kSentinel;
+        if (key != kSentinel && e < keff) {
+            const uint32_t i = key_index(key);
+            const float* y = xb + (int64_t)i * d;
+            float s = 0.f;
+            if (vec) {
+                for (int t = 0; t < d; t += 4) {
+                    const float4 yv = *reinterpret_cast<const float4*>(y + t);
+                    const float4 xv = *reinterpret_cast<const float4*>(&xs[wave][t]);
+                    if (l2) {
+                        float a = xv.x - yv.x, b = xv.y - yv.y, c = xv.z - yv.z, dd = xv.w - yv.w;
+                        s = fmaf(a, a, s);
+                        s = fmaf(b, b, s);
+                        s = fmaf(c, c, s);
+                        s = fmaf(dd, dd, s);
+                    } else {
+                        s = fmaf(xv.x, yv.x, s);
+                        s = fmaf(xv.y, yv.y, s);
+                        s = fmaf(xv.z, yv.z, s);
+                        s = fmaf(xv.w, yv.w, s);
+                    }
+                }
+            } else {
+                for (int t = 0; t < d; ++t) {
+                    if (l2) {
+                        const float a = xs[wave][t] - y[t];
+                        s = fmaf(a, a, s);
+                    } else {
+                        s = fmaf(xs[wave][t], y[t], s);
+                    }
+                }
+            }
+            nk[r] = make_key(l2 ? s : -s, i);
+        }
+    }
+    bitonic_sort<false, KR>(nk);
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const int e = r * 64 + lane;
+        if (e < k) {
+            const uint64_t key = nk[r];
+            if (key == kSentinel) {
+                D[q * k + e] = l2 ? INFINITY : -INFINITY;
+                I[q * k + e] = -1;
+            } else {
+                const float s = key_score(key);
+                D[q * k + e] = l2 ? s : -s;
+                I[q * k + e] = (int64_t)key_index(key);
+            }
+        }
+    }
+}
+
+
+}  // namespace mk
