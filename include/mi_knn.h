@@ -139,6 +139,44 @@ mk_status mk_pq_encode(const float* r, int64_t n, int32_t d, int32_t M, const fl
                        uint8_t* codes, mk_stream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Low-precision brute force with exact re-rank (an extension of the exact
+ * search of Section 5.1; the paper computes distances in FP32 only).
+ * ------------------------------------------------------------------------ */
+typedef enum { MK_PREC_FP32 = 0, MK_PREC_BF16 = 1, MK_PREC_FP8E4M3 = 2 } mk_precision;
+
+/* Row stride, in elements, of low-precision copies: d rounded up to 16. */
+int32_t mk_lowp_stride(int32_t d);
+
+/*
+ * Low-precision copy of n rows of dimension d (d <= 256):
+ *   MK_PREC_BF16:    out [n, ld] of BF16 (2 bytes, round to nearest even);
+ *   MK_PREC_FP8E4M3: out [n, ld] of OCP E4M3 (1 byte, round to nearest even)
+ *                    of the row multiplied by a power of two s_i with
+ *                    max_t |x_it| s_i in (224, 448] (s_i = 1 for a zero row);
+ *                    inv_scales [n] float32 receives 1 / s_i.
+ * ld = mk_lowp_stride(d); elements d..ld-1 are zero.  inv_scales may be NULL
+ * for BF16 (otherwise it receives 1).
+ */
+mk_status mk_quantize_rows(const float* x, int64_t n, int32_t d, int32_t prec, void* out,
+                           float* inv_scales, mk_stream_t stream);
+
+/*
+ * Brute-force k-NN whose q.y term runs on BF16 or FP8-E4M3 matrix cores with
+ * FP32 accumulation (queries quantized inside the call as above, the FP8
+ * product rescaled by both rows' 1/s): the rerank_R best candidates per query
+ * by that approximate score are kept, their distances are recomputed from the
+ * FP32 rows in the direct form, and the k best of them are returned exactly
+ * as mk_knn_search reports them.
+ *   xq [nq, d], xb [nb, d] float32; xb_lp / xb_inv: mk_quantize_rows(xb);
+ *   yn [nb] FP32 norms of xb (L2; NULL: computed); k <= rerank_R <= 1024.
+ *   D [nq, k] float32, I [nq, k] int64.
+ */
+mk_status mk_knn_search_lowp(const float* xq, int64_t nq, const float* xb, const void* xb_lp,
+                             const float* xb_inv, const float* yn, int64_t nb, int32_t d,
+                             int32_t k, int32_t rerank_R, mk_metric metric, int32_t prec,
+                             float* D, int64_t* I, mk_stream_t stream);
+
+/* ------------------------------------------------------------------------
  * IVFADC index (Section 2 Eq. 3-6; Section 5.2-5.3): coarse quantizer q1
  * with nlist centroids, product quantizer q2 with M sub-quantizers of 256
  * centroids (8-bit codes) on the residual y - q1(y), inverted lists holding

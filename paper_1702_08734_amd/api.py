@@ -53,11 +53,16 @@ _SIGS = {
     "mk_ivfpq_get_quantizers": [_vp, _vp, _vp],
     "mk_ivfpq_set_quantizers": [_vp, _vp, _vp, _vp],
     "mk_ivfpq_get_lists": [_vp, _vp, _vp, _vp],
+    "mk_lowp_stride": [_i32],
+    "mk_quantize_rows": [_vp, _i64, _i32, _i32, _vp, _vp, _vp],
+    "mk_knn_search_lowp": [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _i32,
+                           _vp, _vp, _vp],
     "mk_profile_enable": [_i32],
     "mk_profile_read": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)],
 }
 _RESTYPE = {"mk_last_error": ctypes.c_char_p, "mk_ivfpq_destroy": None,
-            "mk_ivfpq_ntotal": ctypes.c_int64}
+            "mk_ivfpq_ntotal": ctypes.c_int64, "mk_lowp_stride": ctypes.c_int32}
+PRECISIONS = {"bf16": 1, "fp8": 2}
 
 
 def lib():
@@ -142,6 +147,38 @@ def knn_search(xq: torch.Tensor, xb: torch.Tensor, k: int, metric: str = "l2",
         _dev(yn, torch.float32, "yn")
         _call("mk_knn_search_prenorm", _ptr(xq), nq, _ptr(xb), _ptr(yn), nb, d, k,
               METRICS[metric], _ptr(D), _ptr(I), _stream())
+    return D, I
+
+
+def quantize_rows(x: torch.Tensor, prec: str):
+    """Low-precision copy of the rows of x: (uint8 tensor [n, ld * bytes],
+    float32 1/scale per row)."""
+    _dev(x, torch.float32, "x")
+    n, d = x.shape
+    ld = int(lib().mk_lowp_stride(d))
+    nbytes = 2 if prec == "bf16" else 1
+    out = _out((n, ld * nbytes), torch.uint8, x)
+    inv = _out((n,), torch.float32, x)
+    _call("mk_quantize_rows", _ptr(x), n, d, PRECISIONS[prec], _ptr(out), _ptr(inv), _stream())
+    return out, inv
+
+
+def knn_search_lowp(xq: torch.Tensor, xb: torch.Tensor, xb_lp: torch.Tensor, xb_inv: torch.Tensor,
+                    k: int, rerank: int, prec: str, metric: str = "l2",
+                    yn: torch.Tensor | None = None):
+    """Low-precision brute force + exact FP32 re-rank of `rerank` candidates."""
+    _dev(xq, torch.float32, "xq")
+    _dev(xb, torch.float32, "xb")
+    _dev(xb_lp, torch.uint8, "xb_lp")
+    _dev(xb_inv, torch.float32, "xb_inv")
+    nq, d = xq.shape
+    nb = xb.shape[0]
+    D = _out((nq, k), torch.float32, xq)
+    I = _out((nq, k), torch.int64, xq)
+    if yn is not None:
+        _dev(yn, torch.float32, "yn")
+    _call("mk_knn_search_lowp", _ptr(xq), nq, _ptr(xb), _ptr(xb_lp), _ptr(xb_inv), _ptr(yn), nb,
+          d, k, rerank, METRICS[metric], PRECISIONS[prec], _ptr(D), _ptr(I), _stream())
     return D, I
 
 

@@ -43,6 +43,12 @@ const char* get_error();
         }                                                                            \
     } while (0)
 
+#define MK_TRY(expr)                  \
+    do {                              \
+        mk_status st_ = (expr);       \
+        if (st_ != MK_OK) return st_; \
+    } while (0)
+
 // Stream-ordered device scratch; freed on the same stream when it goes out of
 // scope, so a call never synchronises to release it.
 struct Scratch {

@@ -48,12 +48,6 @@ mk_status alloc_dev(T*& p, size_t count) {
     return MK_OK;
 }
 
-#define MK_TRY(expr)                  \
-    do {                              \
-        mk_status st_ = (expr);       \
-        if (st_ != MK_OK) return st_; \
-    } while (0)
-
 // ---------------------------------------------------------------- k-means
 __global__ void gather_rows_kernel(const float* __restrict__ src, int32_t d,
                                    const int64_t* __restrict__ rows, int64_t n,

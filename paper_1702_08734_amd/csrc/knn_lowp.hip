@@ -1,0 +1,193 @@
+// Low-precision brute force with exact re-rank: the q.y term on BF16 or
+// OCP-E4M3 FP8 matrix cores with FP32 accumulation selects rerank_R
+// candidates per query (fused with the selection as in the FP32 path), whose
+// distances are then recomputed from the FP32 rows in the direct form and
+// re-ranked to the final k.  The paper computes distances in FP32 only
+// (Section 2); this is the reduced-precision variant of its exact search.
+#include <cmath>
+
+#include "fused.hpp"
+
+namespace mk {
+
+namespace {
+
+inline int32_t lowp_stride(int32_t d) { return (d + 15) / 16 * 16; }
+
+inline int elem_bytes(int32_t prec) { return prec == 1 ? 2 : 1; }
+
+// BF16 by round-to-nearest-even of the FP32 bits.
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// One wave per row: BF16 copy, or FP8 copy of the row scaled by the power of
+// two s with max|x| s in (224, 448] (s = 1 for an all-zero row), writing
+// 1/s.  Padding elements up to the stride are zero.
+template <int PREC>
+__global__ __launch_bounds__(256) void quantize_rows_kernel(const float* __restrict__ x, int64_t n,
+                                                            int32_t d, int32_t ld,
+                                                            void* __restrict__ out,
+                                                            float* __restrict__ inv_scale) {
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = lane_id();
+    if (row >= n) return;
+    const float* xr = x + row * d;
+    if constexpr (PREC == 1) {
+        uint16_t* o = static_cast<uint16_t*>(out) + row * ld;
+        for (int t = lane; t < ld; t += 64) o[t] = t < d ? to_bf16(xr[t]) : (uint16_t)0;
+        if (inv_scale && lane == 0) inv_scale[row] = 1.f;
+    } else {
+        float m = 0.f;
+        for (int t = lane; t < d; t += 64) m = fmaxf(m, fabsf(xr[t]));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+        double sc = 1.0;
+        if (m > 0.f) {
+            int e;
+            frexp(448.0 / (double)m, &e);  // 448/m = f 2^e, f in [0.5, 1)
+            sc = ldexp(1.0, e - 1);        // largest power of two <= 448/m
+        }
+        const float s = (float)sc;
+        uint16_t* o = reinterpret_cast<uint16_t*>(static_cast<uint8_t*>(out) + row * ld);
+        for (int t2 = lane; 2 * t2 < ld; t2 += 64) {
+            const int t = 2 * t2;
+            const float a = t < d ? xr[t] * s : 0.f;
+            const float b = t + 1 < d ? xr[t + 1] * s : 0.f;
+            o[t2] = (uint16_t)(__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xFFFF);
+        }
+        if (inv_scale && lane == 0) inv_scale[row] = (float)(1.0 / sc);
+    }
+}
+
+mk_status quantize(const float* x, int64_t n, int32_t d, int32_t prec, void* out, float* inv,
+                   hipStream_t s) {
+    if (n == 0) return MK_OK;
+    const int32_t ld = lowp_stride(d);
+    const dim3 grid((unsigned)ceil_div(n, 4)), block(256);
+    if (prec == 1)
+        hipLaunchKernelGGL(quantize_rows_kernel<1>, grid, block, 0, s, x, n, d, ld, out, inv);
+    else
+        hipLaunchKernelGGL(quantize_rows_kernel<2>, grid, block, 0, s, x, n, d, ld, out, inv);
+    MK_LAUNCHED();
+    return MK_OK;
+}
+
+template <class Op, int KR, int DP>
+mk_status lowp_launch(const float* xq, const void* xq_lp, const float* xq_inv, int64_t nq,
+                      const float* xb, const void* xb_lp, const float* xb_inv, const float* yn,
+                      int64_t nb, int32_t d, int32_t k, int32_t R, bool l2, float* D, int64_t* I,
+                      hipStream_t stream) {
+    using S = FusedShape<KR, DP * Op::BYTES>;
+    constexpr int KS = 64 * KR;
+    int64_t nqb, nchunks, chunk_len;
+    plan_chunks(nq, nb, S::BQ, S::BN, KS, &nqb, &nchunks, &chunk_len);
+    Scratch part;
+    mk_status st = part.alloc(sizeof(uint64_t) * (size_t)nq * (size_t)nchunks * KS, stream);
+    if (st != MK_OK) return st;
+    const int64_t nblocks = nqb * nchunks;
+    MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
+    const int32_t ld = lowp_stride(d);
+    FusedArgs a{xq_lp, xb_lp, yn, xq_inv, xb_inv, nq, nb, ld, ld, chunk_len, (int32_t)nchunks,
+                (int32_t)nqb, R, part.as<uint64_t>()};
+    {
+        ProfScope prof(Op::SCALED ? "knn_fused_fp8" : "knn_fused_bf16", stream);
+        auto kern = l2 ? knn_fused<Op, KR, DP, true, true> : knn_fused<Op, KR, DP, true, false>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(64 * (kProducers + S::NC)), 0,
+                           stream, a);
+        MK_LAUNCHED();
+    }
+    const bool vec = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(xq) % 16 == 0) &&
+                     (reinterpret_cast<uintptr_t>(xb) % 16 == 0);
+    {
+        ProfScope prof("knn_merge_rerank", stream);
+        hipLaunchKernelGGL((knn_merge_rerank<KR>), dim3((unsigned)ceil_div(nq, kMergeWaves)),
+                           dim3(64 * kMergeWaves), 0, stream, part.as<uint64_t>(),
+                           (int32_t)nchunks, xq, nq, xb, d, (int32_t)vec, (int32_t)l2, k, R, D, I);
+        MK_LAUNCHED();
+    }
+    return MK_OK;
+}
+
+template <class Op, int DP>
+mk_status lowp_dispatch_k(const float* xq, const void* xq_lp, const float* xq_inv, int64_t nq,
+                          const float* xb, const void* xb_lp, const float* xb_inv,
+                          const float* yn, int64_t nb, int32_t d, int32_t k, int32_t R, bool l2,
+                          float* D, int64_t* I, hipStream_t s) {
+    switch (queue_regs(R)) {
+        case 1: return lowp_launch<Op, 1, DP>(xq, xq_lp, xq_inv, nq, xb, xb_lp, xb_inv, yn, nb, d, k, R, l2, D, I, s);
+        case 2: return lowp_launch<Op, 2, DP>(xq, xq_lp, xq_inv, nq, xb, xb_lp, xb_inv, yn, nb, d, k, R, l2, D, I, s);
+        case 4: return lowp_launch<Op, 4, DP>(xq, xq_lp, xq_inv, nq, xb, xb_lp, xb_inv, yn, nb, d, k, R, l2, D, I, s);
+        case 8: return lowp_launch<Op, 8, DP>(xq, xq_lp, xq_inv, nq, xb, xb_lp, xb_inv, yn, nb, d, k, R, l2, D, I, s);
+        default: return lowp_launch<Op, 16, DP>(xq, xq_lp, xq_inv, nq, xb, xb_lp, xb_inv, yn, nb, d, k, R, l2, D, I, s);
+    }
+}
+
+mk_status search_lowp(const float* xq, int64_t nq, const float* xb, const void* xb_lp,
+                      const float* xb_inv, const float* yn_in, int64_t nb, int32_t d, int32_t k,
+                      int32_t R, mk_metric metric, int32_t prec, float* D, int64_t* I,
+                      hipStream_t s) {
+    const bool l2 = metric == MK_METRIC_L2;
+    const int32_t ld = lowp_stride(d);
+    Scratch qlp, qinv, norms;
+    MK_TRY(qlp.alloc((size_t)nq * ld * elem_bytes(prec), s));
+    MK_TRY(qinv.alloc(sizeof(float) * (size_t)nq, s));
+    MK_TRY(quantize(xq, nq, d, prec, qlp.ptr, qinv.as<float>(), s));
+    const float* yn = yn_in;
+    if (l2 && !yn && nb > 0) {
+        MK_TRY(norms.alloc(sizeof(float) * (size_t)nb, s));
+        MK_TRY(launch_norms(xb, nb, d, norms.as<float>(), s));
+        yn = norms.as<float>();
+    }
+    if (prec == 1) {
+        if (ld <= 32) return lowp_dispatch_k<OpBF16, 32>(xq, qlp.ptr, qinv.as<float>(), nq, xb, xb_lp, xb_inv, yn, nb, d, k, R, l2, D, I, s);
+        if (ld <= 64) return lowp_dispatch_k<OpBF16, 64>(xq, qlp.ptr, qinv.as<float>(), nq, xb, xb_lp, xb_inv, yn, nb, d, k, R, l2, D, I, s);
+        if (ld <= 96) return lowp_dispatch_k<OpBF16, 96>(xq, qlp.ptr, qinv.as<float>(), nq, xb, xb_lp, xb_inv, yn, nb, d, k, R, l2, D, I, s);
+        if (ld <= 128) return lowp_dispatch_k<OpBF16, 128>(xq, qlp.ptr, qinv.as<float>(), nq, xb, xb_lp, xb_inv, yn, nb, d, k, R, l2, D, I, s);
+        return lowp_dispatch_k<OpBF16, 256>(xq, qlp.ptr, qinv.as<float>(), nq, xb, xb_lp, xb_inv, yn, nb, d, k, R, l2, D, I, s);
+    }
+    if (ld <= 64) return lowp_dispatch_k<OpFP8, 64>(xq, qlp.ptr, qinv.as<float>(), nq, xb, xb_lp, xb_inv, yn, nb, d, k, R, l2, D, I, s);
+    if (ld <= 128) return lowp_dispatch_k<OpFP8, 128>(xq, qlp.ptr, qinv.as<float>(), nq, xb, xb_lp, xb_inv, yn, nb, d, k, R, l2, D, I, s);
+    return lowp_dispatch_k<OpFP8, 256>(xq, qlp.ptr, qinv.as<float>(), nq, xb, xb_lp, xb_inv, yn, nb, d, k, R, l2, D, I, s);
+}
+
+}  // namespace
+
+}  // namespace mk
+
+extern "C" int32_t mk_lowp_stride(int32_t d) { return mk::lowp_stride(d); }
+
+extern "C" mk_status mk_quantize_rows(const float* x, int64_t n, int32_t d, int32_t prec,
+                                      void* out, float* inv_scales, mk_stream_t stream) {
+    MK_REQUIRE(n >= 0 && d >= 1, MK_ERR_INVALID_ARG, "need n >= 0 and d >= 1");
+    MK_REQUIRE(prec == MK_PREC_BF16 || prec == MK_PREC_FP8E4M3, MK_ERR_INVALID_ARG,
+               "precision must be BF16 or FP8-E4M3");
+    MK_REQUIRE(d <= 256, MK_ERR_UNSUPPORTED, "d must be <= 256");
+    if (n == 0) return MK_OK;
+    MK_REQUIRE(x && out && (inv_scales || prec == MK_PREC_BF16), MK_ERR_INVALID_ARG,
+               "null pointer");
+    return mk::quantize(x, n, d, prec, out, inv_scales, static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_knn_search_lowp(const float* xq, int64_t nq, const float* xb,
+                                        const void* xb_lp, const float* xb_inv, const float* yn,
+                                        int64_t nb, int32_t d, int32_t k, int32_t rerank_R,
+                                        mk_metric metric, int32_t prec, float* D, int64_t* I,
+                                        mk_stream_t stream) {
+    MK_REQUIRE(nq >= 0 && nb >= 0, MK_ERR_INVALID_ARG, "nq and nb must be >= 0");
+    MK_REQUIRE(d >= 1, MK_ERR_INVALID_ARG, "d must be >= 1");
+    MK_REQUIRE(d <= 256, MK_ERR_UNSUPPORTED, "d must be <= 256");
+    MK_REQUIRE(k >= 1 && rerank_R >= k, MK_ERR_INVALID_ARG, "need 1 <= k <= rerank_R");
+    MK_REQUIRE(rerank_R <= mk::kMaxK, MK_ERR_UNSUPPORTED, "rerank_R must be <= 1024");
+    MK_REQUIRE(nb < (1ll << 31), MK_ERR_UNSUPPORTED, "nb must be < 2^31");
+    MK_REQUIRE(metric == MK_METRIC_L2 || metric == MK_METRIC_IP, MK_ERR_INVALID_ARG, "bad metric");
+    MK_REQUIRE(prec == MK_PREC_BF16 || prec == MK_PREC_FP8E4M3, MK_ERR_INVALID_ARG,
+               "precision must be BF16 or FP8-E4M3");
+    if (nq == 0) return MK_OK;
+    MK_REQUIRE(xq && D && I && (nb == 0 || (xb && xb_lp && (xb_inv || prec == MK_PREC_BF16))),
+               MK_ERR_INVALID_ARG, "null pointer");
+    return mk::search_lowp(xq, nq, xb, xb_lp, xb_inv, yn, nb, d, k, rerank_R, metric, prec, D, I,
+                           static_cast<hipStream_t>(stream));
+}
