@@ -228,6 +228,24 @@ mk_status mk_ivfpq_search(mk_ivfpq* index, const float* xq, int64_t nq, int32_t 
                           int32_t nprobe, float* D, int64_t* I, mk_stream_t stream);
 
 /*
+ * IVFADC search as above for a short list of the R best entries by ADC
+ * distance, then an exact re-rank of that list: each entry's squared L2
+ * distance is recomputed in FP32 from the full-precision database row
+ * xb[id] (direct form, as in mk_knn_search) and the k best by
+ * (distance, id) are returned.  The re-rank is an extension of Algorithm 4,
+ * not part of it: ADC distances are only accurate to the quantisation error,
+ * which bounds how well neighbours inside one cluster can be told apart.
+ *   xq [nq, d], xb [nb, d] float32 (device; nb >= ntotal, row i is the
+ *   vector added with id i), D [nq, k] float32, I [nq, k] int64.
+ * 1 <= k <= R <= 1024; the LDS bound of mk_ivfpq_search holds with R in
+ * place of k.  Entries short of R (probed lists too short) are skipped;
+ * a tail with fewer than k candidates is padded with (+inf, -1).
+ */
+mk_status mk_ivfpq_search_rerank(mk_ivfpq* index, const float* xq, int64_t nq, int32_t k,
+                                 int32_t nprobe, int32_t R, const float* xb, int64_t nb,
+                                 float* D, int64_t* I, mk_stream_t stream);
+
+/*
  * Copy the trained quantizers to host arrays (any pointer may be NULL):
  *   coarse [nlist, d] float32, codebooks [M, 256, d/M] float32.
  * Synchronises.

@@ -265,3 +265,28 @@ def ivfpq_search(xq, coarse, codebooks, offsets, codes, ids, k: int, nprobe: int
         codes, ids_a, k, nprobe,
         npq.ctypes.data_as(ctypes.c_void_p) if npq is not None else None, D, I), "ivfpq_search")
     return D, I
+
+
+def ivfpq_search_rerank(xq, coarse, codebooks, offsets, codes, ids, xb, k: int, nprobe: int,
+                        R: int):
+    """IVFADC short list re-ranked exactly (an extension of Algorithm 4).
+
+    The R best entries by ADC distance (``ivfpq_search`` with k = R) are
+    re-scored by their exact squared L2 distance to the database row of their
+    id (float64 direct form) and the first k by (distance, id) are returned,
+    padded with (+inf, -1) where fewer than k entries were scanned.
+    """
+    xq = _f32(xq)
+    xb = _f32(xb)
+    _, Ia = ivfpq_search(xq, coarse, codebooks, offsets, codes, ids, R, nprobe)
+    nq = xq.shape[0]
+    D = np.full((nq, k), np.inf)
+    I = np.full((nq, k), -1, np.int64)
+    for j in range(nq):
+        cand = Ia[j][Ia[j] >= 0]
+        diff = xb[cand].astype(np.float64) - xq[j].astype(np.float64)
+        dist = (diff * diff).sum(1)
+        order = np.lexsort((cand, dist))[:k]
+        D[j, :len(order)] = dist[order]
+        I[j, :len(order)] = cand[order]
+    return D, I

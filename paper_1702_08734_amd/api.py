@@ -50,6 +50,7 @@ _SIGS = {
     "mk_ivfpq_add": [_vp, _vp, _i64, _vp],
     "mk_ivfpq_ntotal": [_vp],
     "mk_ivfpq_search": [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp],
+    "mk_ivfpq_search_rerank": [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _i64, _vp, _vp, _vp],
     "mk_ivfpq_get_quantizers": [_vp, _vp, _vp],
     "mk_ivfpq_set_quantizers": [_vp, _vp, _vp, _vp],
     "mk_ivfpq_get_lists": [_vp, _vp, _vp, _vp],
@@ -254,6 +255,19 @@ class IVFPQ:
         D = _out((nq, k), torch.float32, xq)
         I = _out((nq, k), torch.int64, xq)
         _call("mk_ivfpq_search", self._h, _ptr(xq), nq, k, nprobe, _ptr(D), _ptr(I), _stream())
+        return D, I
+
+    def search_rerank(self, xq: torch.Tensor, k: int, nprobe: int, R: int, xb: torch.Tensor):
+        """ADC short list of R entries, re-ranked exactly against xb[id]."""
+        _dev(xq, torch.float32, "xq")
+        _dev(xb, torch.float32, "xb")
+        if xb.dim() != 2 or xb.shape[1] != self.d or xq.dim() != 2 or xq.shape[1] != self.d:
+            raise ValueError(f"xq and xb must be [n, {self.d}]")
+        nq = xq.shape[0]
+        D = _out((nq, k), torch.float32, xq)
+        I = _out((nq, k), torch.int64, xq)
+        _call("mk_ivfpq_search_rerank", self._h, _ptr(xq), nq, k, nprobe, R, _ptr(xb),
+              xb.shape[0], _ptr(D), _ptr(I), _stream())
         return D, I
 
     def get_quantizers(self):

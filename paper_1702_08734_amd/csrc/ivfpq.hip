@@ -678,6 +678,33 @@ mk_status search(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t k, int32_t n
     return merge_key_lists(part.as<uint64_t>(), nq, nprobe, k, D, I, s);
 }
 
+// IVFADC short list of R entries per query, then exact re-ranking of that
+// list against the full-precision database rows (row id of xb = vector id).
+mk_status search_rerank(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t k, int32_t nprobe,
+                        int32_t R, const float* xb, float* D, int64_t* I, hipStream_t s) {
+    const int32_t M = ix->M;
+    Scratch cd, ci, t3, part, keys;
+    MK_TRY(cd.alloc(sizeof(float) * nq * nprobe, s));
+    MK_TRY(ci.alloc(sizeof(int64_t) * nq * nprobe, s));
+    MK_TRY(t3.alloc(sizeof(float) * nq * M * 256, s));
+    MK_TRY(part.alloc(sizeof(uint64_t) * nq * nprobe * R, s));
+    MK_TRY(keys.alloc(sizeof(uint64_t) * nq * 64 * queue_regs(R), s));
+    MK_TRY(knn_search(xq, nq, ix->coarse, ix->coarse_norms, ix->nlist, ix->d, nprobe,
+                      MK_METRIC_L2, cd.as<float>(), ci.as<int64_t>(), s));
+    hipLaunchKernelGGL(term3_kernel, dim3(grid_of(nq * M * 256)), dim3(kBlock), 0, s, xq, nq, M,
+                       ix->dsub, ix->books, t3.as<float>());
+    MK_LAUNCHED();
+    MK_TRY(launch_scan(ix->term1, t3.as<float>(), cd.as<float>(), ci.as<int64_t>(),
+                       ix->offsets_dev, ix->codes, ix->ids, M, nq, nprobe, R,
+                       part.as<uint64_t>(), s));
+    {
+        ProfScope prof("ivf_merge", s);
+        MK_TRY(merge_key_lists(part.as<uint64_t>(), nq, nprobe, R, nullptr, nullptr, s,
+                               keys.as<uint64_t>()));
+    }
+    return rerank_keys(keys.as<uint64_t>(), nq, R, xq, xb, ix->d, true, k, D, I, s);
+}
+
 }  // namespace
 
 }  // namespace mk
@@ -779,6 +806,25 @@ extern "C" mk_status mk_ivfpq_search(mk_ivfpq* ix, const float* xq, int64_t nq, 
     if (nq == 0) return MK_OK;
     MK_REQUIRE(xq && D && I, MK_ERR_INVALID_ARG, "null pointer");
     return mk::search(ix, xq, nq, k, nprobe, D, I, static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_ivfpq_search_rerank(mk_ivfpq* ix, const float* xq, int64_t nq,
+                                            int32_t k, int32_t nprobe, int32_t R,
+                                            const float* xb, int64_t nb, float* D, int64_t* I,
+                                            mk_stream_t stream) {
+    MK_REQUIRE(ix, MK_ERR_INVALID_ARG, "null index");
+    MK_REQUIRE(ix->trained, MK_ERR_STATE, "index is not trained");
+    MK_REQUIRE(nq >= 0, MK_ERR_INVALID_ARG, "nq must be >= 0");
+    MK_REQUIRE(k >= 1 && k <= R, MK_ERR_INVALID_ARG, "need 1 <= k <= R");
+    MK_REQUIRE(R <= mk::kMaxK, MK_ERR_UNSUPPORTED, "R must be <= 1024");
+    MK_REQUIRE(nprobe >= 1 && nprobe <= ix->nlist && nprobe <= mk::kMaxK, MK_ERR_INVALID_ARG,
+               "need 1 <= nprobe <= min(nlist, 1024)");
+    MK_REQUIRE(nb >= ix->ntotal, MK_ERR_INVALID_ARG,
+               "the database must hold a row for every added id");
+    if (nq == 0) return MK_OK;
+    MK_REQUIRE(xq && D && I && (xb || nb == 0), MK_ERR_INVALID_ARG, "null pointer");
+    return mk::search_rerank(ix, xq, nq, k, nprobe, R, xb, D, I,
+                             static_cast<hipStream_t>(stream));
 }
 
 extern "C" mk_status mk_ivfpq_get_quantizers(const mk_ivfpq* ix, float* coarse, float* codebooks) {

@@ -133,6 +133,35 @@ mk_status knn_search(const float* xq, int64_t nq, const float* xb, const float* 
     return knn_dispatch_k<256>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
 }
 
+template <int KR>
+mk_status rerank_launch(const uint64_t* keys, int64_t nq, int32_t R, const float* xq,
+                        const float* xb, int32_t d, bool l2, bool vec, int32_t k, float* D,
+                        int64_t* I, hipStream_t s) {
+    ProfScope prof("rerank", s);
+    hipLaunchKernelGGL((knn_merge_rerank<KR>), dim3((unsigned)ceil_div(nq, kMergeWaves)),
+                       dim3(64 * kMergeWaves), 0, s, keys, 1, xq, nq, xb, d, (int32_t)vec,
+                       (int32_t)l2, k, R, D, I);
+    MK_LAUNCHED();
+    return MK_OK;
+}
+
+mk_status rerank_keys(const uint64_t* keys, int64_t nq, int32_t R, const float* xq,
+                      const float* xb, int32_t d, bool l2, int32_t k, float* D, int64_t* I,
+                      hipStream_t s) {
+    MK_REQUIRE(d >= 1 && d <= kMaxDim, MK_ERR_UNSUPPORTED, "re-rank needs 1 <= d <= 512");
+    MK_REQUIRE(k >= 1 && k <= R && R <= kMaxK, MK_ERR_INVALID_ARG, "need 1 <= k <= R <= 1024");
+    if (nq == 0) return MK_OK;
+    const bool vec = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(xq) % 16 == 0) &&
+                     (reinterpret_cast<uintptr_t>(xb) % 16 == 0);
+    switch (queue_regs(R)) {
+        case 1: return rerank_launch<1>(keys, nq, R, xq, xb, d, l2, vec, k, D, I, s);
+        case 2: return rerank_launch<2>(keys, nq, R, xq, xb, d, l2, vec, k, D, I, s);
+        case 4: return rerank_launch<4>(keys, nq, R, xq, xb, d, l2, vec, k, D, I, s);
+        case 8: return rerank_launch<8>(keys, nq, R, xq, xb, d, l2, vec, k, D, I, s);
+        default: return rerank_launch<16>(keys, nq, R, xq, xb, d, l2, vec, k, D, I, s);
+    }
+}
+
 }  // namespace mk
 
 extern "C" mk_status mk_norms(const float* x, int64_t n, int32_t d, float* out,

@@ -128,11 +128,12 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_pass1(
     }
 }
 
-// Pass 2: per row, select the k best of nseg * k partial keys.
+// Pass 2: per row, select the k best of nseg * k partial keys, written as
+// (value, index) pairs or, with keys_out, as the 64*KR-entry sorted key list.
 template <int KR, int T, bool LARGEST>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_merge(
     const uint64_t* __restrict__ partial, int64_t nrows, int32_t nseg, int32_t k,
-    float* __restrict__ vals, int64_t* __restrict__ idx) {
+    float* __restrict__ vals, int64_t* __restrict__ idx, uint64_t* __restrict__ keys_out) {
     const int wave = threadIdx.x / 64;
     const int lane = lane_id();
     const int64_t row = (int64_t)blockIdx.x * kWavesPerBlock + wave;
@@ -147,7 +148,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_merge(
         if (ws.push(i < n ? p[i] : kSentinel)) ws.merge();
     }
     ws.finish();
-    emit_values<KR, LARGEST>(ws.w, k, vals + row * k, idx + row * k);
+    if (keys_out)
+        emit_keys<KR>(ws.w, 64 * KR, keys_out + row * 64 * KR);
+    else
+        emit_values<KR, LARGEST>(ws.w, k, vals + row * k, idx + row * k);
 }
 
 template <int KR, int T, bool LARGEST>
@@ -182,7 +186,8 @@ mk_status kselect_launch(const float* a, int64_t nrows, int64_t len, int32_t k, 
     if (nseg > 1) {
         hipLaunchKernelGGL((kselect_merge<KR, T, LARGEST>),
                            dim3((unsigned)ceil_div(nrows, kWavesPerBlock)), dim3(64 * kWavesPerBlock),
-                           0, stream, part.as<uint64_t>(), nrows, (int32_t)nseg, k, vals, idx);
+                           0, stream, part.as<uint64_t>(), nrows, (int32_t)nseg, k, vals, idx,
+                           (uint64_t*)nullptr);
         MK_LAUNCHED();
     }
     return MK_OK;
@@ -203,20 +208,20 @@ mk_status kselect_dispatch(const float* a, int64_t nrows, int64_t len, int32_t k
 }  // namespace
 
 mk_status merge_key_lists(const uint64_t* partial, int64_t nrows, int32_t nseg, int32_t k,
-                          float* vals, int64_t* idx, hipStream_t s) {
+                          float* vals, int64_t* idx, hipStream_t s, uint64_t* keys_out) {
     if (nrows == 0) return MK_OK;
     const dim3 grid((unsigned)ceil_div(nrows, kWavesPerBlock)), block(64 * kWavesPerBlock);
     switch (queue_regs(k)) {
         case 1: hipLaunchKernelGGL((kselect_merge<1, SelParams<1>::T, false>), grid, block, 0, s,
-                                   partial, nrows, nseg, k, vals, idx); break;
+                                   partial, nrows, nseg, k, vals, idx, keys_out); break;
         case 2: hipLaunchKernelGGL((kselect_merge<2, SelParams<2>::T, false>), grid, block, 0, s,
-                                   partial, nrows, nseg, k, vals, idx); break;
+                                   partial, nrows, nseg, k, vals, idx, keys_out); break;
         case 4: hipLaunchKernelGGL((kselect_merge<4, SelParams<4>::T, false>), grid, block, 0, s,
-                                   partial, nrows, nseg, k, vals, idx); break;
+                                   partial, nrows, nseg, k, vals, idx, keys_out); break;
         case 8: hipLaunchKernelGGL((kselect_merge<8, SelParams<8>::T, false>), grid, block, 0, s,
-                                   partial, nrows, nseg, k, vals, idx); break;
+                                   partial, nrows, nseg, k, vals, idx, keys_out); break;
         default: hipLaunchKernelGGL((kselect_merge<16, SelParams<16>::T, false>), grid, block, 0,
-                                    s, partial, nrows, nseg, k, vals, idx); break;
+                                    s, partial, nrows, nseg, k, vals, idx, keys_out); break;
     }
     MK_LAUNCHED();
     return MK_OK;

@@ -31,15 +31,26 @@ template <> struct SelParams<8> { static constexpr int T = 4; };
 template <> struct SelParams<16> { static constexpr int T = 8; };
 
 // Per row, select the k best of nseg sorted lists of k keys each
-// (partial[row][seg][k]) and write (score, index) pairs; sentinel keys become
-// (+inf, -1).  The second pass of the two-pass k-selection of Section 5.3.
+// (partial[row][seg][k]) and write (score, index) pairs -- sentinel keys
+// become (+inf, -1) -- or, if keys_out is given, the sorted keys themselves
+// (keys_out[row][64 * queue_regs(k)], sentinel padded).  The second pass of
+// the two-pass k-selection of Section 5.3.
 mk_status merge_key_lists(const uint64_t* partial, int64_t nrows, int32_t nseg, int32_t k,
-                          float* vals, int64_t* idx, hipStream_t s);
+                          float* vals, int64_t* idx, hipStream_t s,
+                          uint64_t* keys_out = nullptr);
 
 // Exact k-NN (knn.hip); yn may be null (then computed) for L2.
 mk_status knn_search(const float* xq, int64_t nq, const float* xb, const float* yn, int64_t nb,
                      int32_t d, int32_t k, mk_metric metric, float* D, int64_t* I,
                      hipStream_t s);
 mk_status launch_norms(const float* x, int64_t n, int32_t d, float* out, hipStream_t s);
+
+// Exact re-rank of candidate lists: keys[row] holds 64 * queue_regs(R) keys
+// whose first R are the row's candidates (score, database row); each
+// candidate is re-scored in the FP32 direct form against xb (rows of d
+// floats) and the k best by (distance, row) are written to D, I.
+mk_status rerank_keys(const uint64_t* keys, int64_t nq, int32_t R, const float* xq,
+                      const float* xb, int32_t d, bool l2, int32_t k, float* D, int64_t* I,
+                      hipStream_t s);
 
 }  // namespace mk

@@ -139,4 +139,4 @@ def ivfpq_workload(nb: int = 10_000_000, nq: int = 10_000, nt: int = 500_000):
     return {"xb": xb, "xq": xq, "sample": sample, "nlist": 4096, "M": 16,
             "coarse_init": choose_rows(nt, 4096, (103, 3)),
             "pq_init": pq_init_rows(nt, 16, (103, 4)), "k": 100,
-            "nprobes": (1, 8, 32, 128)}
+            "nprobes": (1, 8, 16, 32, 64, 128), "rerank": (256, 1024)}

@@ -283,6 +283,95 @@ def test_ivfpq_handworked(api, golden_dir):
         np.testing.assert_allclose(D.cpu().numpy()[0], exp, rtol=1e-6)
 
 
+def test_ivfpq_rerank_handworked(api, golden_dir):
+    with open(os.path.join(golden_dir, "ivfpq_rerank_handworked.json")) as f:
+        g = json.load(f)
+    d, M = g["d"], g["M"]
+    # embedded in d = 8, M = 4 as in the plain hand-worked case
+    D8, M4 = 8, 4
+    ds = d // M
+    books = np.full((M4, 256, ds), 100.0, np.float32)
+    for m, entries in g["codebook_set"].items():
+        for j, v in entries.items():
+            books[int(m), int(j)] = v
+    books[2:, 0] = 0.0
+    coarse = np.zeros((2, D8), np.float32)
+    coarse[:, :d] = np.array(g["coarse"], np.float32)
+    xb = np.zeros((len(g["xb"]), D8), np.float32)
+    xb[:, :d] = np.array(g["xb"], np.float32)
+    xq = np.zeros((1, D8), np.float32)
+    xq[0, :d] = g["query"]
+    ix = api.IVFPQ(D8, 2, M4)
+    ix.set_quantizers(coarse, books)
+    b = dev(xb)
+    ix.add(b)
+    for c in g["cases"]:
+        say(f"rerank handworked {c}")
+        D, I = ix.search_rerank(dev(xq), c["k"], c["nprobe"], c["R"], b)
+        assert I.cpu().numpy()[0].tolist() == c["I"]
+        exp = [float("inf") if v == "inf" else v for v in c["D"]]
+        np.testing.assert_allclose(D.cpu().numpy()[0], exp, rtol=1e-6)
+
+
+@pytest.mark.parametrize("k,nprobe,R", [(1, 4, 16), (10, 8, 100), (100, 16, 400), (10, 64, 1024)])
+def test_ivfpq_rerank_matches_oracle(api, small_index, k, nprobe, R):
+    say(f"ivfpq rerank k={k} nprobe={nprobe} R={R}")
+    ix, xq, xb = small_index["ix"], small_index["xq"], small_index["xb"]
+    D, I = ix.search_rerank(dev(xq), k, nprobe, R, dev(xb))
+    torch.cuda.synchronize()
+    coarse, books = ix.get_quantizers()
+    offs, codes, ids = ix.get_lists()
+    rows = np.arange(0, 300, 5)
+    # short lists whose R-th ADC value is band-ambiguous may legitimately
+    # differ; the oracle's R + 1 values tell which rows those are
+    Da, Ia = oracle.ivfpq_search(xq[rows], coarse, books, offs, codes, ids, R + 1, nprobe)
+    Do, Io = oracle.ivfpq_search_rerank(xq[rows], coarse, books, offs, codes, ids, xb, k,
+                                        nprobe, R)
+    Dg, Ig = D.cpu().numpy()[rows], I.cpu().numpy()[rows]
+    skipped, fails = 0, []
+    for j, q in enumerate(rows):
+        x = xq[q].astype(np.float64)
+        cd = np.sort(((coarse.astype(np.float64) - x) ** 2).sum(1))
+        probe_amb = nprobe < len(coarse) and cd[nprobe] - cd[nprobe - 1] <= RTOL * cd[nprobe]
+        a = Da[j]
+        list_amb = Ia[j, R] >= 0 and a[R] - a[R - 1] <= RTOL * a[R]
+        if probe_amb or list_amb:
+            skipped += 1
+            continue
+        gi = Ig[j][Ig[j] >= 0]
+        nexp = int((Io[j] >= 0).sum())
+        if len(gi) != nexp:
+            fails.append(f"q{q}: {len(gi)} results, expected {nexp}")
+            continue
+        # exact FP32 distances of the returned rows
+        delta = ((xb[gi].astype(np.float64) - x) ** 2).sum(1)
+        gd = Dg[j][:nexp].astype(np.float64)
+        floor = 1e-3 * ((x ** 2).sum() + (xb[gi].astype(np.float64) ** 2).sum(1))
+        if np.any(np.abs(gd - delta) > RTOL * np.maximum(delta, floor)):
+            fails.append(f"q{q}: distance off")
+        od, oi = Do[j][:nexp], Io[j][:nexp]
+        dk = od[-1]
+        band_ids = set(oi[np.abs(od - dk) <= RTOL * dk].tolist())
+        if not (set(oi.tolist()) - band_ids) <= set(gi.tolist()):
+            fails.append(f"q{q}: sets differ beyond the band")
+        for r in range(nexp):
+            lo = r == 0 or od[r] - od[r - 1] > RTOL * od[r]
+            hi = r + 1 >= nexp or od[r + 1] - od[r] > RTOL * od[r]
+            if lo and hi and gi[r] != oi[r]:
+                fails.append(f"q{q}: rank {r} id {gi[r]} != oracle {oi[r]}")
+                break
+    assert not fails, fails[:10]
+    assert skipped <= 3
+
+
+def test_ivfpq_rerank_errors(api, small_index):
+    ix, xq, xb = small_index["ix"], small_index["xq"], small_index["xb"]
+    with pytest.raises(api.MKError):
+        ix.search_rerank(dev(xq[:2]), 10, 4, 5, dev(xb))          # R < k
+    with pytest.raises(api.MKError):
+        ix.search_rerank(dev(xq[:2]), 10, 4, 20, dev(xb[:100]))   # too few rows
+
+
 def test_ivfpq_state_errors(api):
     ix = api.IVFPQ(16, 8, 4)
     with pytest.raises(api.MKError) as e:

@@ -246,6 +246,22 @@ def test_ivfpq_handworked(golden_dir):
     assert x @ q2 == e["term3"]
 
 
+def test_ivfpq_rerank_handworked(golden_dir):
+    g = _load(golden_dir, "ivfpq_rerank_handworked.json")
+    coarse, books = _handworked_index(g)
+    xb = np.array(g["xb"], np.float32)
+    lists, codes = oracle.ivf_encode(xb, coarse, books)
+    assert lists.tolist() == g["lists"]
+    assert codes.tolist() == g["codes"]
+    offs, lc, lid = oracle.build_lists(lists, codes, len(coarse))
+    q = np.array([g["query"]], np.float32)
+    for c in g["cases"]:
+        D, I = oracle.ivfpq_search_rerank(q, coarse, books, offs, lc, lid, xb, c["k"],
+                                          c["nprobe"], c["R"])
+        assert I[0].tolist() == c["I"]
+        np.testing.assert_allclose(D[0], [_num(v) for v in c["D"]], rtol=1e-6)
+
+
 def _random_index(seed, nlist=6, M=4, ds=2, nb=300):
     rng = np.random.default_rng(seed)
     d = M * ds
@@ -329,6 +345,32 @@ def test_ivfpq_lossless_equals_exact():
     De, Ie = oracle.knn(xq, xb, 30)
     np.testing.assert_array_equal(I, Ie)
     np.testing.assert_array_equal(D, De)
+
+
+def test_ivfpq_rerank_full_list_is_exact_search():
+    # every entry probed and short-listed: the re-rank is exact search
+    xq, xb, coarse, books, lists, codes, offs, lc, lid = _random_index(34)
+    for k in (1, 7, 50):
+        D, I = oracle.ivfpq_search_rerank(xq, coarse, books, offs, lc, lid, xb, k,
+                                          len(coarse), len(xb))
+        De, Ie = oracle.knn(xq, xb, k)
+        np.testing.assert_array_equal(I, Ie)
+        np.testing.assert_allclose(D, De, rtol=1e-12)
+
+
+def test_ivfpq_rerank_short_list():
+    # results are the exact-distance order of the ADC short list of length R
+    xq, xb, coarse, books, lists, codes, offs, lc, lid = _random_index(35)
+    k, R, nprobe = 5, 12, 2
+    Da, Ia = oracle.ivfpq_search(xq, coarse, books, offs, lc, lid, R, nprobe)
+    D, I = oracle.ivfpq_search_rerank(xq, coarse, books, offs, lc, lid, xb, k, nprobe, R)
+    exact = cdist(xq.astype(np.float64), xb.astype(np.float64), "sqeuclidean")
+    for j in range(len(xq)):
+        cand = Ia[j][Ia[j] >= 0]
+        assert set(I[j].tolist()) <= set(cand.tolist())
+        ref = sorted((exact[j, i], i) for i in cand)[:k]
+        assert I[j].tolist() == [i for _, i in ref]
+        np.testing.assert_allclose(D[j], [v for v, _ in ref], rtol=1e-12)
 
 
 def test_build_lists_insertion_order_and_append():
