@@ -35,7 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 FP32_MFMA_PEAK_TFLOPS = 157.3
 KS = (1, 32, 256, 1024)
 PMC_FILE = os.path.join(ROOT, "profiles", "knn_fused_exact_large_pmc.json")
-KERNEL_SOURCES = ["knn.hip", "wave_select.hpp", "kselect.hpp"]
+KERNEL_SOURCES = ["knn.hip", "fused.hpp", "wave_select.hpp", "kselect.hpp"]
 
 
 def kernel_source_hash() -> str:
@@ -170,11 +170,14 @@ def ivfpq_section(api, synth, torch):
             rerank.append({"nprobe": nprobe, "R": R, "ms": round(dt * 1e3, 3),
                            "qps": round(nq / dt, 1), "recall_at_10": r1,
                            "ten_intersection": r2})
+    learned = learned_probe_section(api, synth, torch, ix, xb, xq, w, recalls)
+    serving = serving_section(api, synth, torch, ix, xb, xq, w, learned)
     del xb
     torch.cuda.empty_cache()
     best = [c for c in curve if c["recall_at_10"] >= 0.9]
     best_rr = sorted((c for c in rerank if c["recall_at_10"] >= 0.9), key=lambda c: -c["qps"])
-    return {"workload": "10,000,000 x 128 mixture, nlist 4096, PQ 16 x 8 bit, 10,000 queries, "
+    return {"learned_probe": learned, "serving": serving,
+            "workload": "10,000,000 x 128 mixture, nlist 4096, PQ 16 x 8 bit, 10,000 queries, "
                         "k = 100 (ADC) / k = 10 after exact re-rank of R, "
                         "train 500,000 rows x 20 iterations",
             "train_s": round(t_train, 2), "add_s": round(t_add, 2),
@@ -187,6 +190,132 @@ def ivfpq_section(api, synth, torch):
                                                  "R": best_rr[0]["R"]} if best_rr else None)}
 
 
+def learned_probe_section(api, synth, torch, ix, xb, xq, w, recalls):
+    """Learned per-query probe count vs the best fixed probe count, both with
+    the same exact re-rank depth, at recall@10 >= 0.9 (true nearest
+    neighbour among the 10 returned)."""
+    import numpy as np
+    R, cap, k, nq = w["learn_rerank"], w["learn_cap"], 10, xq.shape[0]
+    # fixed probe counts with the same re-rank depth
+    fixed = []
+    for nprobe in w["learn_fixed_nprobes"]:
+        dt = _timed(torch, lambda: ix.search_rerank(xq, k, nprobe, R, xb), 3)
+        r1, r2 = recalls(ix.search_rerank(xq, k, nprobe, R, xb)[1])
+        fixed.append({"nprobe": nprobe, "ms": round(dt * 1e3, 3), "qps": round(nq / dt, 1),
+                      "recall_at_10": r1, "ten_intersection": r2})
+    progress("learned probe: labels for training queries")
+    mix = synth.Mixture(1000, 128, (103, 99))
+    xtr = torch.from_numpy(mix.sample(w["learn_train"], (103, 20))).cuda()
+    nn = torch.cat([api.knn_search(xtr[i:i + 20000], xb, 1)[1][:, 0]
+                    for i in range(0, xtr.shape[0], 20000)]).contiguous()
+    F = ix.probe_features(xtr)
+    target, label = ix.probe_labels(xtr, nn, cap)
+    net = api.MLP(128 + 32, 256, "bf16")
+    net.set_params(synth.mlp_init(160, 256, (103, 21)))
+    net.fit_standardization(F)
+    progress("learned probe: training")
+    t0 = time.perf_counter()
+    losses = []
+    for ep in range(w["learn_epochs"]):
+        perm = torch.from_numpy(synth.permutation(F.shape[0], (103, 22, ep))).cuda()
+        losses.append(float(net.train_epoch(F, target, perm, 1024, 1e-3).mean().item()))
+    t_train = time.perf_counter() - t0
+    # calibrate the offset on held-out queries: smallest delta reaching 0.9
+    progress("learned probe: calibration")
+    xcal = torch.from_numpy(mix.sample(10_000, (103, 23))).cuda()
+    gcal = api.knn_search(xcal, xb, 1)[1][:, 0].cpu().numpy()
+    delta = None
+    for dlt in np.arange(-1.0, 4.01, 0.25):
+        I = ix.search_learned(net, float(dlt), xcal, k, cap, R, xb)[1].cpu().numpy()
+        if np.mean([gcal[j] in I[j] for j in range(len(gcal))]) >= 0.9:
+            delta = float(dlt)
+            break
+    out = {"train_queries": int(xtr.shape[0]), "epochs": w["learn_epochs"],
+           "epoch_loss": [round(v, 4) for v in losses], "train_s": round(t_train, 2),
+           "label_mean": round(float(label.float().mean().item()), 2), "R": R, "cap": cap,
+           "fixed": fixed, "delta": delta}
+    best_fixed = [c for c in fixed if c["recall_at_10"] >= 0.9]
+    out["qps_fixed_at_0.9"] = max((c["qps"] for c in best_fixed), default=None)
+    if delta is not None:
+        dt = _timed(torch, lambda: ix.search_learned(net, delta, xq, k, cap, R, xb), 3)
+        _, I, tau = ix.search_learned(net, delta, xq, k, cap, R, xb)
+        r1, r2 = recalls(I)
+        out.update({"ms": round(dt * 1e3, 3), "qps_learned": round(nq / dt, 1),
+                    "recall_at_10": r1, "ten_intersection": r2,
+                    "mean_nprobe": round(float(tau.float().mean().item()), 2)})
+    out["net"] = net
+    return out
+
+
+def serving_section(api, synth, torch, ix, xb, xq, w, learned):
+    """Continuous batching under Poisson arrivals: requests of log-uniform size
+    in [1, 1024] rows, k = 10, exact re-rank; latency percentiles per rate."""
+    import threading
+    import numpy as np
+    net = learned.pop("net", None)
+    R, k = w["learn_rerank"], 10
+    delta = learned.get("delta")
+    cfg = {"R": R, "xb": xb, "max_batch": 1024, "nstreams": 2}
+    if net is not None and delta is not None:
+        cfg.update({"net": net, "delta": delta, "cap": w["learn_cap"]})
+        mode = "learned probe count"
+    else:
+        best = [c for c in learned["fixed"] if c["recall_at_10"] >= 0.9]
+        cfg["nprobe"] = best[0]["nprobe"] if best else max(w["learn_fixed_nprobes"])
+        mode = f"fixed probe count {cfg['nprobe']}"
+    xq_h = xq.cpu().numpy()
+    nreq = w["serve_requests"]
+    rng = np.random.default_rng(np.random.SeedSequence((103, 24)))
+    sizes = np.clip(np.floor(np.exp(rng.random(nreq) * np.log(1025))), 1, 1024).astype(int)
+    starts = rng.integers(0, xq_h.shape[0] - 1024, nreq)
+    gaps = rng.exponential(1.0, nreq)
+    # saturated throughput: everything submitted at once
+    srv = api.Server(ix, k, **cfg)
+    t0 = time.perf_counter()
+    tk = [srv.submit(xq_h[s:s + n]) for s, n in zip(starts, sizes)]
+    for t in tk:
+        srv.wait(t)
+    peak_rows = sizes.sum() / (time.perf_counter() - t0)
+    srv.close()
+    res = {"mode": mode, "requests": nreq, "mean_rows": round(float(sizes.mean()), 1),
+           "saturated_rows_per_s": round(float(peak_rows), 1), "rates": []}
+    for frac in w["serve_load"]:
+        progress(f"serving: load {frac}")
+        lam = frac * peak_rows / sizes.mean()  # requests per second
+        srv = api.Server(ix, k, **cfg)
+        tickets = [None] * nreq
+        lat = [0.0] * nreq
+        done = threading.Event()
+
+        def collect():
+            for i in range(nreq):
+                while tickets[i] is None:
+                    time.sleep(1e-4)
+                lat[i] = srv.wait(tickets[i])[2]
+            done.set()
+
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        t_arr = t0
+        for i in range(nreq):
+            t_arr += gaps[i] / lam
+            pause = t_arr - time.perf_counter()
+            if pause > 0:
+                time.sleep(pause)
+            tickets[i] = srv.submit(xq_h[starts[i]:starts[i] + sizes[i]])
+        th.join()
+        wall = time.perf_counter() - t0
+        nb, _ = srv.stats()
+        srv.close()
+        ms = np.array(lat) * 1e3
+        res["rates"].append({"load": frac, "offered_rows_per_s": round(float(lam * sizes.mean()), 1),
+                             "achieved_rows_per_s": round(float(sizes.sum() / wall), 1),
+                             "batches": nb, "p50_ms": round(float(np.percentile(ms, 50)), 3),
+                             "p99_ms": round(float(np.percentile(ms, 99)), 3)})
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +325,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip-extra", action="store_true",
                     help="only the exact-search measurement (for profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device (HBM byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are "
@@ -203,6 +334,14 @@ def main() -> int:
         return 2
 
     import torch
+    if args.copy_calibration:
+        x = torch.ones(1 << 28, device="cuda")  # 1 GiB read + 1 GiB written by one copy
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}))
+        return 0
     from paper_1702_08734_amd import api, synth
 
     progress("exact: generating 1,000,000 x 128 mixture")

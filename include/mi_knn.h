@@ -270,6 +270,159 @@ mk_status mk_ivfpq_get_lists(const mk_ivfpq* index, int64_t* offsets, uint8_t* c
 
 
 /* ------------------------------------------------------------------------
+ * Learned probe count.  An extension of the fixed probe count tau of
+ * Section 2 (Eq. 5 probes the tau nearest coarse centroids of every query):
+ * a perceptron with two ReLU hidden layers predicts log2(tau) per query from
+ * the query and its 32 smallest squared coarse distances, and the search
+ * probes tau_q = clamp(ceil(2^(prediction + delta)), 1, cap) lists.
+ * Features are standardised per column with a stored mean and standard
+ * deviation before the first layer.  Matrix products run on the matrix cores
+ * in FP32 or BF16 (FP32 accumulation); weights, gradients and the Adam
+ * moments are FP32.  All arrays are device memory unless stated otherwise.
+ * ------------------------------------------------------------------------ */
+
+typedef struct mk_mlp mk_mlp;
+
+/*
+ * din inputs (d + 32 for an index of dimension d), hidden units per layer,
+ * prec MK_PREC_FP32 or MK_PREC_BF16.  Parameters start at zero and the
+ * standardisation at mean 0, deviation 1.
+ */
+mk_status mk_mlp_create(int32_t din, int32_t hidden, mk_precision prec, mk_mlp** out);
+void mk_mlp_destroy(mk_mlp* net);
+
+/* Length of the flat parameter vector: W1 [hidden, din] row-major, b1
+ * [hidden], W2 [hidden, hidden], b2 [hidden], w3 [hidden], b3 [1]. */
+int64_t mk_mlp_num_params(const mk_mlp* net);
+
+/* Load parameters from a host array (the caller draws the initial values);
+ * resets the Adam moments and step count.  Synchronises. */
+mk_status mk_mlp_set_params(mk_mlp* net, const float* theta);
+
+/* Copy parameters and the last gradient to host arrays (either may be
+ * NULL).  Synchronises. */
+mk_status mk_mlp_get_params(const mk_mlp* net, float* theta, float* grad);
+
+/* Per-column mean and population standard deviation (FP64 sums; a column
+ * without spread gets deviation 1) of n raw feature rows F [n, din]. */
+mk_status mk_mlp_fit_standardization(mk_mlp* net, const float* F, int64_t n,
+                                     mk_stream_t stream);
+
+/* Copy the stored means and 1/deviations to host arrays [din] (either may
+ * be NULL).  Synchronises. */
+mk_status mk_mlp_get_standardization(const mk_mlp* net, float* mean, float* inv_std);
+
+/* yhat [n] = network(standardised F [n, din]). */
+mk_status mk_mlp_forward(const mk_mlp* net, const float* F, int64_t n, float* yhat,
+                         mk_stream_t stream);
+
+/*
+ * Mean squared error of the batch rows F[rows[i]] (rows may be NULL: rows
+ * 0 .. B-1) against targets y[rows[i]], and its gradient, which is kept as
+ * the network's last gradient (read it with mk_mlp_get_params).  loss: a
+ * device float, may be NULL.
+ */
+mk_status mk_mlp_loss_grad(mk_mlp* net, const float* F, const int64_t* rows, int64_t B,
+                           const float* y, float* loss, mk_stream_t stream);
+
+/*
+ * One pass over n rows in the order perm [n] (a permutation drawn by the
+ * caller): batches of `batch` rows, each a forward pass, the gradient of
+ * its mean squared error and one Adam step (beta1 0.9, beta2 0.999,
+ * eps 1e-8, learning rate lr).  losses: device floats, one per batch, may
+ * be NULL.
+ */
+mk_status mk_mlp_train_epoch(mk_mlp* net, const float* F, int64_t n, const float* y,
+                             const int64_t* perm, int32_t batch, float lr, float* losses,
+                             mk_stream_t stream);
+
+/* Raw network features of nq queries: F [nq, d + 32] = [xq ; the 32
+ * smallest squared coarse distances, ascending].  Needs nlist >= 32. */
+mk_status mk_ivfpq_probe_features(const mk_ivfpq* index, const float* xq, int64_t nq, float* F,
+                                  mk_stream_t stream);
+
+/*
+ * Training labels: for query q with nearest-neighbour id nn_ids[q], the
+ * 1-based rank of the list holding that id in the query's coarse order
+ * (cap when it is not among the first cap); label [nq] int32 (may be NULL)
+ * and target [nq] float = log2(label).  1 <= cap <= min(nlist, 1024).
+ */
+mk_status mk_ivfpq_probe_labels(const mk_ivfpq* index, const float* xq, int64_t nq,
+                                const int64_t* nn_ids, int32_t cap, float* target,
+                                int32_t* label, mk_stream_t stream);
+
+/*
+ * IVFADC search probing tau_q lists per query (see above) with
+ * 32 <= cap <= min(nlist, 1024).  R = 0: ADC distances as in
+ * mk_ivfpq_search; R >= k: exact re-rank of an R-entry short list against
+ * xb [nb, d] as in mk_ivfpq_search_rerank.  nprobe_used [nq] int32 (may be
+ * NULL) receives tau_q.  Synchronises once (to size the list-scan launch).
+ */
+mk_status mk_ivfpq_search_learned(mk_ivfpq* index, const mk_mlp* net, float delta,
+                                  const float* xq, int64_t nq, int32_t k, int32_t cap, int32_t R,
+                                  const float* xb, int64_t nb, float* D, int64_t* I,
+                                  int32_t* nprobe_used, mk_stream_t stream);
+
+/* Dimension d of an index. */
+int32_t mk_ivfpq_dim(const mk_ivfpq* index);
+
+/*
+ * Upper bound on the device workspace (bytes) that one search of nq queries
+ * allocates: mk_ivfpq_search (R = 0), mk_ivfpq_search_rerank (R > 0) or
+ * mk_ivfpq_search_learned (nprobe = cap).  Used for admission control.
+ */
+mk_status mk_ivfpq_search_workspace_bytes(const mk_ivfpq* index, int64_t nq, int32_t k,
+                                          int32_t nprobe, int32_t R, size_t* bytes);
+
+/* ------------------------------------------------------------------------
+ * Serving loop (continuous batching; not part of the paper).  Requests of
+ * host query rows are queued and packed in arrival order into batches of at
+ * most max_batch rows whose search workspace stays within workspace_budget
+ * bytes (the first request of a batch is always admitted); nstreams
+ * batches are in flight at once, each on its own HIP stream with pinned
+ * staging buffers, so transfers and kernels of consecutive batches overlap.
+ * A request's results equal those of searching it alone.
+ * ------------------------------------------------------------------------ */
+
+typedef struct mk_server mk_server;
+
+typedef struct {
+    int32_t k;                /* neighbours per query */
+    int32_t nprobe;           /* probe count when net is NULL */
+    int32_t R;                /* > 0: exact re-rank depth (needs xb) */
+    int32_t max_batch;        /* rows per batch (and per request) */
+    int32_t nstreams;         /* batches in flight, 1 .. 8 */
+    int32_t cap;              /* learned probe count: largest tau */
+    float delta;              /* learned probe count: offset */
+    const mk_mlp* net;        /* non-NULL: learned probe count */
+    const float* xb;          /* device database rows for the re-rank */
+    int64_t nb;
+    int64_t workspace_budget; /* device bytes per batch; 0: no limit */
+} mk_server_config;
+
+/* Start the loop's threads on the current device; the index (and net, xb)
+ * must outlive the server. */
+mk_status mk_server_create(mk_ivfpq* index, const mk_server_config* cfg, mk_server** out);
+
+/*
+ * Queue nq query rows xq [nq, d] (host) with result buffers D [nq, k],
+ * I [nq, k] (host); all three stay owned by the caller and must stay valid
+ * until mk_server_wait returns for the ticket.  1 <= nq <= max_batch.
+ */
+mk_status mk_server_submit(mk_server* server, const float* xq, int64_t nq, float* D,
+                           int64_t* I, uint64_t* ticket);
+
+/* Block until the request completes; latency_s (may be NULL) receives the
+ * time from submission to completion.  Each ticket is collected once. */
+mk_status mk_server_wait(mk_server* server, uint64_t ticket, double* latency_s);
+
+/* Batches launched and rows searched so far (either may be NULL). */
+mk_status mk_server_stats(mk_server* server, int64_t* batches, int64_t* rows);
+
+/* Finish every queued request, stop the threads, free the buffers. */
+void mk_server_destroy(mk_server* server);
+
+/* ------------------------------------------------------------------------
  * Kernel timing.  While enabled, every launch of the library's main kernels
  * is bracketed by a pair of HIP events recorded on the launch stream, so the
  * measured time is that kernel's own execution on the device.

@@ -58,10 +58,33 @@ _SIGS = {
     "mk_quantize_rows": [_vp, _i64, _i32, _i32, _vp, _vp, _vp],
     "mk_knn_search_lowp": [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _i32,
                            _vp, _vp, _vp],
+    "mk_mlp_create": [_i32, _i32, _i32, ctypes.POINTER(_vp)],
+    "mk_mlp_destroy": [_vp],
+    "mk_mlp_num_params": [_vp],
+    "mk_mlp_set_params": [_vp, _vp],
+    "mk_mlp_get_params": [_vp, _vp, _vp],
+    "mk_mlp_fit_standardization": [_vp, _vp, _i64, _vp],
+    "mk_mlp_get_standardization": [_vp, _vp, _vp],
+    "mk_mlp_forward": [_vp, _vp, _i64, _vp, _vp],
+    "mk_mlp_loss_grad": [_vp, _vp, _vp, _i64, _vp, _vp, _vp],
+    "mk_mlp_train_epoch": [_vp, _vp, _i64, _vp, _vp, _i32, _f32, _vp, _vp],
+    "mk_ivfpq_probe_features": [_vp, _vp, _i64, _vp, _vp],
+    "mk_ivfpq_probe_labels": [_vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp],
+    "mk_ivfpq_search_learned": [_vp, _vp, _f32, _vp, _i64, _i32, _i32, _i32, _vp, _i64, _vp, _vp,
+                                _vp, _vp],
+    "mk_ivfpq_dim": [_vp],
+    "mk_ivfpq_search_workspace_bytes": [_vp, _i64, _i32, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)],
+    "mk_server_create": [_vp, _vp, ctypes.POINTER(_vp)],
+    "mk_server_submit": [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)],
+    "mk_server_wait": [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)],
+    "mk_server_stats": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+    "mk_server_destroy": [_vp],
     "mk_profile_enable": [_i32],
     "mk_profile_read": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)],
 }
-_RESTYPE = {"mk_last_error": ctypes.c_char_p, "mk_ivfpq_destroy": None,
+_RESTYPE = {"mk_last_error": ctypes.c_char_p, "mk_ivfpq_destroy": None, "mk_mlp_destroy": None,
+            "mk_mlp_num_params": ctypes.c_int64, "mk_ivfpq_dim": ctypes.c_int32,
+            "mk_server_destroy": None,
             "mk_ivfpq_ntotal": ctypes.c_int64, "mk_lowp_stride": ctypes.c_int32}
 PRECISIONS = {"bf16": 1, "fp8": 2}
 
@@ -270,6 +293,45 @@ class IVFPQ:
               xb.shape[0], _ptr(D), _ptr(I), _stream())
         return D, I
 
+    def workspace_bytes(self, nq: int, k: int, nprobe: int, R: int = 0) -> int:
+        b = ctypes.c_size_t()
+        _call("mk_ivfpq_search_workspace_bytes", self._h, nq, k, nprobe, R, ctypes.byref(b))
+        return int(b.value)
+
+    def probe_features(self, xq: torch.Tensor) -> torch.Tensor:
+        """[xq ; its 32 smallest squared coarse distances] per query."""
+        _dev(xq, torch.float32, "xq")
+        F = _out((xq.shape[0], self.d + 32), torch.float32, xq)
+        _call("mk_ivfpq_probe_features", self._h, _ptr(xq), xq.shape[0], _ptr(F), _stream())
+        return F
+
+    def probe_labels(self, xq: torch.Tensor, nn_ids: torch.Tensor, cap: int):
+        """(target = log2(label), label): rank of the list of each query's
+        nearest neighbour in its coarse order, at most cap."""
+        _dev(xq, torch.float32, "xq")
+        _dev(nn_ids, torch.int64, "nn_ids")
+        nq = xq.shape[0]
+        target = _out((nq,), torch.float32, xq)
+        label = _out((nq,), torch.int32, xq)
+        _call("mk_ivfpq_probe_labels", self._h, _ptr(xq), nq, _ptr(nn_ids), cap, _ptr(target),
+              _ptr(label), _stream())
+        return target, label
+
+    def search_learned(self, net: "MLP", delta: float, xq: torch.Tensor, k: int, cap: int,
+                       R: int = 0, xb: torch.Tensor | None = None):
+        """Search with the predicted per-query probe count; (D, I, tau)."""
+        _dev(xq, torch.float32, "xq")
+        if xb is not None:
+            _dev(xb, torch.float32, "xb")
+        nq = xq.shape[0]
+        D = _out((nq, k), torch.float32, xq)
+        I = _out((nq, k), torch.int64, xq)
+        tau = _out((nq,), torch.int32, xq)
+        _call("mk_ivfpq_search_learned", self._h, net._h, delta, _ptr(xq), nq, k, cap, R,
+              _ptr(xb), xb.shape[0] if xb is not None else 0, _ptr(D), _ptr(I), _ptr(tau),
+              _stream())
+        return D, I, tau
+
     def get_quantizers(self):
         import numpy as np
         coarse = np.empty((self.nlist, self.d), np.float32)
@@ -304,3 +366,139 @@ def profile_read(name: str):
     n = _i64()
     _call("mk_profile_read", name.encode(), ctypes.byref(ms), ctypes.byref(n))
     return ms.value, n.value
+
+
+class MLP:
+    """Probe-count predictor: din -> hidden (ReLU) -> hidden (ReLU) -> 1."""
+
+    def __init__(self, din: int, hidden: int, prec: str = "fp32"):
+        self.din, self.hidden = din, hidden
+        h = _vp()
+        _call("mk_mlp_create", din, hidden, {"fp32": 0, "bf16": 1}[prec], ctypes.byref(h))
+        self._h = h
+        self.n_params = int(lib().mk_mlp_num_params(h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.mk_mlp_destroy(h)
+            self._h = None
+
+    def set_params(self, theta) -> None:
+        import numpy as np
+        t = np.ascontiguousarray(theta, np.float32)
+        if t.shape != (self.n_params,):
+            raise ValueError(f"theta must have {self.n_params} entries")
+        _call("mk_mlp_set_params", self._h, t.ctypes.data)
+
+    def get_params(self):
+        """(theta, last gradient) as float32 numpy arrays."""
+        import numpy as np
+        t = np.empty(self.n_params, np.float32)
+        g = np.empty(self.n_params, np.float32)
+        _call("mk_mlp_get_params", self._h, t.ctypes.data, g.ctypes.data)
+        return t, g
+
+    def fit_standardization(self, F: torch.Tensor) -> None:
+        _dev(F, torch.float32, "F")
+        _call("mk_mlp_fit_standardization", self._h, _ptr(F), F.shape[0], _stream())
+
+    def get_standardization(self):
+        import numpy as np
+        m = np.empty(self.din, np.float32)
+        s = np.empty(self.din, np.float32)
+        _call("mk_mlp_get_standardization", self._h, m.ctypes.data, s.ctypes.data)
+        return m, s
+
+    def forward(self, F: torch.Tensor) -> torch.Tensor:
+        _dev(F, torch.float32, "F")
+        y = _out((F.shape[0],), torch.float32, F)
+        _call("mk_mlp_forward", self._h, _ptr(F), F.shape[0], _ptr(y), _stream())
+        return y
+
+    def loss_grad(self, F: torch.Tensor, y: torch.Tensor, rows: torch.Tensor | None = None):
+        """Batch loss (device scalar); the gradient stays in the network."""
+        _dev(F, torch.float32, "F")
+        _dev(y, torch.float32, "y")
+        if rows is not None:
+            _dev(rows, torch.int64, "rows")
+        B = rows.shape[0] if rows is not None else F.shape[0]
+        loss = _out((1,), torch.float32, F)
+        _call("mk_mlp_loss_grad", self._h, _ptr(F), _ptr(rows), B, _ptr(y), _ptr(loss),
+              _stream())
+        return loss
+
+    def train_epoch(self, F: torch.Tensor, y: torch.Tensor, perm: torch.Tensor, batch: int,
+                    lr: float = 1e-3) -> torch.Tensor:
+        _dev(F, torch.float32, "F")
+        _dev(y, torch.float32, "y")
+        _dev(perm, torch.int64, "perm")
+        n = F.shape[0]
+        losses = _out(((n + batch - 1) // batch,), torch.float32, F)
+        _call("mk_mlp_train_epoch", self._h, _ptr(F), n, _ptr(y), _ptr(perm), batch, lr,
+              _ptr(losses), _stream())
+        return losses
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("k", _i32), ("nprobe", _i32), ("R", _i32), ("max_batch", _i32),
+                ("nstreams", _i32), ("cap", _i32), ("delta", _f32), ("net", _vp), ("xb", _vp),
+                ("nb", _i64), ("workspace_budget", _i64)]
+
+
+class Server:
+    """Continuous-batching search loop over a resident IVFPQ index.
+
+    submit() takes host float32 query rows and returns a ticket; wait(ticket)
+    blocks until the request is done and returns (D, I, latency seconds)."""
+
+    def __init__(self, index: IVFPQ, k: int, nprobe: int = 1, R: int = 0, max_batch: int = 1024,
+                 nstreams: int = 2, net: MLP | None = None, delta: float = 0.0, cap: int = 0,
+                 xb: torch.Tensor | None = None, workspace_budget: int = 0):
+        if xb is not None:
+            _dev(xb, torch.float32, "xb")
+        self.index, self.k, self.d = index, k, index.d
+        self._keep = (index, net, xb)
+        cfg = _ServerConfig(k, nprobe, R, max_batch, nstreams, cap, delta,
+                            net._h.value if net is not None else None,
+                            _ptr(xb), xb.shape[0] if xb is not None else 0, workspace_budget)
+        h = _vp()
+        _call("mk_server_create", index._h, ctypes.byref(cfg), ctypes.byref(h))
+        self._h = h
+        self._pending = {}
+
+    def submit(self, xq) -> int:
+        import numpy as np
+        q = np.ascontiguousarray(xq, np.float32)
+        if q.ndim != 2 or q.shape[1] != self.d:
+            raise ValueError(f"xq must be [n, {self.d}]")
+        D = np.empty((q.shape[0], self.k), np.float32)
+        I = np.empty((q.shape[0], self.k), np.int64)
+        t = ctypes.c_uint64()
+        _call("mk_server_submit", self._h, q.ctypes.data, q.shape[0], D.ctypes.data,
+              I.ctypes.data, ctypes.byref(t))
+        self._pending[t.value] = (q, D, I)  # keeps the host buffers alive
+        return t.value
+
+    def wait(self, ticket: int):
+        lat = ctypes.c_double()
+        try:
+            _call("mk_server_wait", self._h, ticket, ctypes.byref(lat))
+        finally:
+            bufs = self._pending.pop(ticket, None)
+        _, D, I = bufs
+        return D, I, lat.value
+
+    def stats(self):
+        b, r = _i64(), _i64()
+        _call("mk_server_stats", self._h, ctypes.byref(b), ctypes.byref(r))
+        return b.value, r.value
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.mk_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -19,62 +19,67 @@ typedef __attribute__((address_space(1))) void* gbl_ptr_t;
 
 // ---------------------------------------------------------------- selectors
 // QW independent selectors held by one wave (one per query the wave owns).
-// Merges run one query at a time through a working copy so that the merge
+// Each queue register r (and each thread-queue slot) is a vector over the QW
+// queries, low and high key halves apart, so that a merge can fetch and
+// store the state of one query chosen at run time with a wave-uniform index
+// (register-relative moves) instead of a select over all of them; the merge
 // network is emitted once, not once per query.
 template <int KR, int T, int QW>
 struct MultiSelect {
-    uint64_t w[QW][KR];
-    uint64_t tq[QW][T];
-    uint64_t kth[QW];
-    float kth_f[QW];
+    static constexpr int kQueries = QW;
+    typedef uint32_t vq __attribute__((ext_vector_type(QW)));
+    typedef float vqf __attribute__((ext_vector_type(QW)));
+    vq wl[KR], wh[KR];   // wave queues
+    vq tl[T], th[T];     // thread queues
+    vq kl, kh;           // key of each query's current k-th entry (wave-uniform)
+    vqf kf;              // its score, or the bound below if that is smaller
+    vqf bd;              // score bound from other database chunks
     int keff;
 
     __device__ __forceinline__ void init(int k_eff) {
         keff = k_eff;
 #pragma unroll
-        for (int q = 0; q < QW; ++q) {
+        for (int r = 0; r < KR; ++r) wl[r] = wh[r] = ~0u;
 #pragma unroll
-            for (int r = 0; r < KR; ++r) w[q][r] = kSentinel;
-#pragma unroll
-            for (int i = 0; i < T; ++i) tq[q][i] = kSentinel;
-            kth[q] = kSentinel;
-            kth_f[q] = INFINITY;
-        }
+        for (int i = 0; i < T; ++i) tl[i] = th[i] = ~0u;
+        kl = kh = ~0u;
+        kf = INFINITY;
+        bd = INFINITY;
     }
 
+    // Candidates scoring above b cannot enter query q's result (another
+    // chunk already holds keff candidates scoring at most b).
+    __device__ __forceinline__ void bound(int q, float b) {
+        bd[q] = fminf(bd[q], b);
+        kf[q] = fminf(kf[q], b);
+    }
+
+    __device__ __forceinline__ uint64_t key(int q, int r) const {
+        return ((uint64_t)wh[r][q] << 32) | wl[r][q];
+    }
+
+    // Merge the thread queues of query q (wave-uniform) into its wave queue.
     __device__ __forceinline__ void merge_slot(int q) {
         uint64_t ww[KR], tt[T];
 #pragma unroll
-        for (int r = 0; r < KR; ++r) ww[r] = opaque(w[0][r]);
+        for (int r = 0; r < KR; ++r) ww[r] = ((uint64_t)wh[r][q] << 32) | wl[r][q];
 #pragma unroll
-        for (int i = 0; i < T; ++i) tt[i] = opaque(tq[0][i]);
-#pragma unroll
-        for (int qq = 1; qq < QW; ++qq) {
-            const bool hit = qq == q;
-#pragma unroll
-            for (int r = 0; r < KR; ++r) {
-                const uint64_t e = opaque(w[qq][r]);
-                ww[r] = hit ? e : ww[r];
-            }
-#pragma unroll
-            for (int i = 0; i < T; ++i) {
-                const uint64_t e = opaque(tq[qq][i]);
-                tt[i] = hit ? e : tt[i];
-            }
-        }
+        for (int i = 0; i < T; ++i) tt[i] = ((uint64_t)th[i][q] << 32) | tl[i][q];
         ws_merge<KR, T>(ww, tt);
         const uint64_t kk = ws_element<KR>(ww, keff - 1);
-        const float kf = kk == kSentinel ? INFINITY : key_score(kk);
 #pragma unroll
-        for (int qq = 0; qq < QW; ++qq) {
-            const bool hit = qq == q;
-#pragma unroll
-            for (int r = 0; r < KR; ++r) w[qq][r] = hit ? opaque(ww[r]) : w[qq][r];
-#pragma unroll
-            for (int i = 0; i < T; ++i) tq[qq][i] = hit ? kSentinel : tq[qq][i];
-            kth[qq] = hit ? kk : kth[qq];
-            kth_f[qq] = hit ? kf : kth_f[qq];
+        for (int r = 0; r < KR; ++r) {
+            wl[r][q] = (uint32_t)ww[r];
+            wh[r][q] = (uint32_t)(ww[r] >> 32);
         }
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            tl[i][q] = ~0u;
+            th[i][q] = ~0u;
+        }
+        kl[q] = (uint32_t)kk;
+        kh[q] = (uint32_t)(kk >> 32);
+        kf[q] = fminf(kk == kSentinel ? INFINITY : key_score(kk), bd[q]);
     }
 
     // Offer, for every query q, this lane's candidate (score[q], idx); ok
@@ -84,12 +89,21 @@ struct MultiSelect {
         uint32_t full = 0;
 #pragma unroll
         for (int q = 0; q < QW; ++q) {
-            if (__any(ok && score[q] <= kth_f[q])) {
+            if (__any(ok && score[q] <= kf[q])) {
                 const uint64_t key = ok ? make_key(score[q], idx) : kSentinel;
-                const bool take = key < kth[q];
+                const uint64_t kth = ((uint64_t)kh[q] << 32) | kl[q];
+                const bool take = key < kth;
                 if (__any(take)) {
-                    tq_push<T>(tq[q], key, take);
-                    if (__any(tq_full<T>(tq[q]))) full |= 1u << q;
+                    uint64_t tq[T];
+#pragma unroll
+                    for (int i = 0; i < T; ++i) tq[i] = ((uint64_t)th[i][q] << 32) | tl[i][q];
+                    tq_push<T>(tq, key, take);
+#pragma unroll
+                    for (int i = 0; i < T; ++i) {
+                        tl[i][q] = (uint32_t)tq[i];
+                        th[i][q] = (uint32_t)(tq[i] >> 32);
+                    }
+                    if (__any(tq_full<T>(tq))) full |= 1u << q;
                 }
             }
         }
@@ -191,9 +205,10 @@ constexpr int kProducers = 4;
 template <int KR, int RB>
 struct FusedShape {
     static constexpr int NC = KR >= 16 ? 8 : 4;
-    // thread-queue length: 4 for 1024-entry queues so that two selectors and
-    // a working copy fit a consumer's registers
-    static constexpr int T = KR >= 16 ? 4 : SelParams<KR>::T;
+    // thread-queue length: shorter than the stand-alone selector's for 256-
+    // and 1024-entry queues so that a consumer's selectors and working copy
+    // fit its registers
+    static constexpr int T = KR >= 16 ? 4 : KR == 4 ? 2 : SelParams<KR>::T;
     static constexpr bool wide = RB > 512;
     static constexpr int QPB = (!wide && KR <= 2) ? 2 : 1;
     static constexpr int DPB = (!wide && KR <= 4) ? 2 : 1;
@@ -218,7 +233,33 @@ struct FusedArgs {
     int64_t chunk_len;
     int32_t nchunks, nqb, keff;
     uint64_t* part;       // [nq][nchunks][64 * KR] keys
+    uint32_t* bound;      // [nq] order-mapped score bound shared by the chunks of a query
 };
+
+// Chunks of one query share a bound on its selection score: every
+// kBoundEvery steps a consumer tightens its queries' filters with the bound
+// published so far and publishes its own k-th score (a valid bound for every
+// chunk of the query: that chunk already holds keff candidates scoring at
+// most that much).  Scores equal to the bound still compete, so the kept set
+// is exactly the one without sharing.
+constexpr int kBoundEvery = 32;
+
+template <class Sel>
+__device__ __forceinline__ void exchange_bounds(Sel& sel, const FusedArgs& a, int64_t qfirst,
+                                                int lane) {
+    if (!a.bound) return;
+#pragma unroll
+    for (int qq = 0; qq < Sel::kQueries; ++qq) {
+        const int64_t q = qfirst + qq;
+        if (q < a.nq) {
+            sel.bound(qq, order_float(__atomic_load_n(a.bound + q, __ATOMIC_RELAXED)));
+            const float mine = sel.kf[qq];
+            if (lane == 0 && mine < INFINITY)
+                __hip_atomic_fetch_min(a.bound + q, float_order(mine + 0.0f), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
 
 template <class Op, int KR, int DP, bool VEC, bool L2>
 __global__ __launch_bounds__(64 * (kProducers + FusedShape<KR, DP * Op::BYTES>::NC))
@@ -226,7 +267,12 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
     using S = FusedShape<KR, DP * Op::BYTES>;
     constexpr int T = S::T;
     constexpr int BQ = S::BQ, BN = S::BN, QW = S::QW, QPB = S::QPB, DPB = S::DPB, DG = S::DG;
-    constexpr int LDP = BN + 4;
+    // Score slot: column-major, LDQ floats per database row (a multiple of 4,
+    // 4 mod 32 words apart) so that producers store four queries of a column
+    // and consumers load their QW queries of a column as 16-byte vectors
+    // without bank conflicts.
+    constexpr int LDQ = BQ + 4 + ((BQ + 4) % 32 == 4 ? 0 : (36 - (BQ + 4) % 32) % 32);
+    static_assert(LDQ % 4 == 0 && QW % 2 == 0, "vector score access");
     constexpr int KS = 64 * KR;
     // Database tile in LDS: BN rows of GR 16-byte granules; granule c of row j
     // is stored at position c ^ (j & SW) so that the 16 rows read by one MFMA
@@ -236,9 +282,11 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
     static_assert(GR % 4 == 0, "padded row must be a multiple of 4 granules");
     constexpr int SW = (GR % 16 == 0) ? 15 : (GR % 8 == 0) ? 7 : 3;
     constexpr int NI = BN * GR / 64;  // 64-lane granule loads per tile
+    constexpr int SK0 = 4 / (QPB * DPB) > 1 ? 4 / (QPB * DPB) : 1;
+    constexpr int SK = SK0 < S4 ? SK0 : S4;
 
     __shared__ __align__(16) uint4 btile[2][BN * GR];
-    __shared__ float scores[2][BQ * LDP];
+    __shared__ __align__(16) float scores[2][BN * LDQ];
 
     const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)args.nqb * args.nchunks);
     const int64_t chunk = logical / args.nqb;
@@ -295,34 +343,45 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
             if (s < nsteps) {
                 if (s + 1 < nsteps) load_tile(c0 + (s + 1) * BN, (int)((s + 1) & 1));
                 const uint4* bt = btile[s & 1];
-                floatx4 acc[QPB][DPB];
+                // All B granules of the step first, so that LDS latency
+                // overlaps the matrix work of earlier granules.
+                uint4 b[S4][DPB];
 #pragma unroll
-                for (int qb = 0; qb < QPB; ++qb)
-#pragma unroll
-                    for (int db = 0; db < DPB; ++db) acc[qb][db] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s4 = 0; s4 < S4; ++s4) {
-                    uint4 b[DPB];
+                for (int s4 = 0; s4 < S4; ++s4)
 #pragma unroll
                     for (int db = 0; db < DPB; ++db) {
                         const int j = (dg * DPB + db) * 16 + li;
-                        b[db] = bt[j * GR + ((4 * s4 + lh) ^ (j & SW))];
+                        b[s4][db] = bt[j * GR + ((4 * s4 + lh) ^ (j & SW))];
                     }
+                // SK independent accumulators per output block (split over
+                // the granule steps) keep at least four MFMA chains in flight.
+                floatx4 acc[SK][QPB][DPB];
+#pragma unroll
+                for (int kk = 0; kk < SK; ++kk)
 #pragma unroll
                     for (int qb = 0; qb < QPB; ++qb)
 #pragma unroll
-                        for (int db = 0; db < DPB; ++db) acc[qb][db] = Op::mma(acc[qb][db], areg[qb][s4], b[db]);
-                }
-                // D[i][j] of a 16x16 block sits in lane j + 16*(i/4), element i%4.
+                        for (int db = 0; db < DPB; ++db) acc[kk][qb][db] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s4 = 0; s4 < S4; ++s4)
+#pragma unroll
+                    for (int qb = 0; qb < QPB; ++qb)
+#pragma unroll
+                        for (int db = 0; db < DPB; ++db)
+                            acc[s4 % SK][qb][db] = Op::mma(acc[s4 % SK][qb][db], areg[qb][s4], b[s4][db]);
+                // D[i][j] of a 16x16 block sits in lane j + 16*(i/4), element
+                // i%4: one 16-byte store of queries 4*lh .. 4*lh+3 of column j.
                 float* slot = scores[s & 1];
 #pragma unroll
                 for (int qb = 0; qb < QPB; ++qb)
 #pragma unroll
-                    for (int db = 0; db < DPB; ++db)
+                    for (int db = 0; db < DPB; ++db) {
+                        floatx4 v = acc[0][qb][db];
 #pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            slot[((qg * QPB + qb) * 16 + 4 * lh + r) * LDP + (dg * DPB + db) * 16 + li] =
-                                acc[qb][db][r];
+                        for (int kk = 1; kk < SK; ++kk) v += acc[kk][qb][db];
+                        const int j = (dg * DPB + db) * 16 + li;
+                        *reinterpret_cast<floatx4*>(&slot[j * LDQ + (qg * QPB + qb) * 16 + 4 * lh]) = v;
+                    }
                 __builtin_amdgcn_s_waitcnt(0);
             }
             __syncthreads();
@@ -348,6 +407,7 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
             if (Op::SCALED) ysnext = args.yinv[c0 + lane];
         }
         for (int64_t s = 0; s <= nsteps; ++s) {
+            if ((s & (kBoundEvery - 1)) == 0 || s == nsteps) exchange_bounds(sel, args, q0 + cw * QW, lane);
             if (s >= 1) {
                 const float* slot = scores[(s - 1) & 1];
                 const int64_t g = c0 + (s - 1) * BN + lane;
@@ -358,9 +418,25 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
                     if (Op::SCALED) ysnext = args.yinv[g + BN];
                 }
                 float score[QW];
+                const float* col = slot + lane * LDQ + cw * QW;
+                if constexpr (QW % 4 == 0) {
+#pragma unroll
+                    for (int qq = 0; qq < QW; qq += 4) {
+                        const floatx4 cc = *reinterpret_cast<const floatx4*>(col + qq);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) score[qq + e] = cc[e];
+                    }
+                } else {
+#pragma unroll
+                    for (int qq = 0; qq < QW; qq += 2) {
+                        const float2 cc = *reinterpret_cast<const float2*>(col + qq);
+                        score[qq] = cc.x;
+                        score[qq + 1] = cc.y;
+                    }
+                }
 #pragma unroll
                 for (int qq = 0; qq < QW; ++qq) {
-                    float c = slot[(cw * QW + qq) * LDP + lane];
+                    float c = score[qq];
                     if (Op::SCALED) c = c * qs[qq] * ysv;
                     score[qq] = L2 ? fmaf(-2.f, c, ynv) : -c;
                 }
@@ -369,16 +445,30 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
             __syncthreads();
         }
         sel.finish();
+        exchange_bounds(sel, args, q0 + cw * QW, lane);
 #pragma unroll
         for (int qq = 0; qq < QW; ++qq) {
             const int64_t q = q0 + cw * QW + qq;
             if (q < args.nq) {
                 uint64_t* out = args.part + (q * args.nchunks + chunk) * KS;
 #pragma unroll
-                for (int r = 0; r < KR; ++r) out[r * 64 + lane] = sel.w[qq][r];
+                for (int r = 0; r < KR; ++r) out[r * 64 + lane] = sel.key(qq, r);
             }
         }
     }
+}
+
+// bound[q] = order-mapped +inf (no bound yet).
+static __global__ void clear_bounds_kernel(uint32_t* __restrict__ bound, int64_t nq) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nq) bound[i] = 0xFF800000u;
+}
+
+inline mk_status clear_bounds(uint32_t* bound, int64_t nq, hipStream_t s) {
+    hipLaunchKernelGGL(clear_bounds_kernel, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, s,
+                       bound, nq);
+    MK_LAUNCHED();
+    return MK_OK;
 }
 
 // Chunking of the database: enough workgroups to fill the chip several times

@@ -11,6 +11,7 @@
 
 #include "common.hpp"
 #include "kselect.hpp"
+#include "mlp.hpp"
 #include "profile.hpp"
 #include "wave_select.hpp"
 
@@ -379,25 +380,96 @@ constexpr int kScanWaves = 4;
 // to its wave's selector keyed by (distance, offset in list) -- offset order
 // is id order inside a list.  The four waves' queues are merged through LDS
 // and the winners' ids resolved (Section 5.3: ids only for the selected).
+// Probe-count features: F[q] = [xq[q] ; the kProbeDists smallest squared
+// coarse distances] (cd holds ld ascending distances per query).
+__global__ void probe_features_kernel(const float* __restrict__ xq, int64_t nq, int32_t d,
+                                      const float* __restrict__ cd, int32_t ld,
+                                      float* __restrict__ F) {
+    const int32_t din = d + kProbeDists;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nq * din) return;
+    const int64_t q = e / din;
+    const int t = (int)(e % din);
+    F[e] = t < d ? xq[q * d + t] : cd[q * ld + (t - d)];
+}
+
+// list_of[id] = inverted list holding id.
+__global__ void list_of_kernel(const int64_t* __restrict__ offsets, int32_t nlist,
+                               const int64_t* __restrict__ ids, int32_t* __restrict__ list_of) {
+    const int32_t L = blockIdx.x;
+    if (L >= nlist) return;
+    for (int64_t pos = offsets[L] + threadIdx.x; pos < offsets[L + 1]; pos += blockDim.x)
+        list_of[ids[pos]] = L;
+}
+
+// Probe count a query needs: 1-based rank of the list holding its nearest
+// neighbour in its coarse order (ld entries per query), cap if not among
+// them; target = log2 of it.
+__global__ void probe_labels_kernel(const int64_t* __restrict__ ci, int32_t ld, int64_t nq,
+                                    const int64_t* __restrict__ nn, const int32_t* __restrict__ list_of,
+                                    int64_t ntotal, int32_t cap, float* __restrict__ target,
+                                    int32_t* __restrict__ label) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const int64_t id = nn[q];
+    int32_t r = cap;
+    if (id >= 0 && id < ntotal) {
+        const int32_t L = list_of[id];
+        for (int32_t p = 0; p < cap && p < ld; ++p)
+            if (ci[q * ld + p] == L) { r = p + 1; break; }
+    }
+    target[q] = log2f((float)r);
+    if (label) label[q] = r;
+}
+
+// tau = clamp(ceil(2^(yhat + delta)), 1, cap) per query; count[q] = tau.
+__global__ void probe_count_kernel(const float* __restrict__ yhat, int64_t nq, float delta,
+                                   int32_t cap, int32_t* __restrict__ tau,
+                                   int64_t* __restrict__ count) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const float t = exp2f(yhat[q] + delta);
+    int32_t v = cap;
+    if (t < (float)cap) v = t <= 1.f ? 1 : (int32_t)ceilf(t);
+    tau[q] = v;
+    count[q] = v;
+}
+
 template <int KR>
 __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
     const float* __restrict__ term1, const float* __restrict__ term3,
     const float* __restrict__ coarse_d, const int64_t* __restrict__ coarse_i,
     const int64_t* __restrict__ offsets, const uint8_t* __restrict__ codes,
     const int64_t* __restrict__ ids, int32_t M, int32_t nprobe, int32_t k,
-    uint64_t* __restrict__ part) {
+    uint64_t* __restrict__ part, const int64_t* __restrict__ work, int64_t nq) {
     constexpr int T = SelParams<KR>::T;
     constexpr int KS = 64 * KR;
     extern __shared__ __align__(16) unsigned char smem[];
     float* lut = reinterpret_cast<float*>(smem);
     uint64_t* qbuf = reinterpret_cast<uint64_t*>(smem + (size_t)M * 256 * sizeof(float));
 
+    // Work item -> (query, probe rank).  Without a work list every query
+    // probes nprobe lists; with one, query q owns items work[q] ..
+    // work[q + 1] - 1 (its own probe count); the coarse results have nprobe
+    // entries per query either way.
     const int64_t item = blockIdx.x;
-    const int64_t q = item / nprobe;
+    int64_t q, p;
+    if (work) {
+        int64_t lo = 0, hi = nq;  // largest q with work[q] <= item
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (work[mid] <= item) lo = mid; else hi = mid;
+        }
+        q = lo;
+        p = item - work[q];
+    } else {
+        q = item / nprobe;
+        p = item - q * nprobe;
+    }
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int64_t L = coarse_i[item];
-    const float term2 = coarse_d[item];
+    const int64_t L = coarse_i[q * nprobe + p];
+    const float term2 = coarse_d[q * nprobe + p];
     uint64_t* out = part + item * k;
 
     if (L < 0) {  // fewer lists than probes: nothing to scan (wave-uniform)
@@ -481,8 +553,9 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
 
 mk_status launch_scan(const float* term1, const float* term3, const float* cd, const int64_t* ci,
                       const int64_t* offsets, const uint8_t* codes, const int64_t* ids, int32_t M,
-                      int64_t nq, int32_t nprobe, int32_t k, uint64_t* part, hipStream_t s) {
-    const int64_t items = nq * nprobe;
+                      int64_t nq, int32_t nprobe, int32_t k, uint64_t* part, hipStream_t s,
+                      const int64_t* work = nullptr, int64_t nwork = 0) {
+    const int64_t items = work ? nwork : nq * nprobe;
     if (items == 0) return MK_OK;
     MK_REQUIRE(items < (1ll << 31), MK_ERR_UNSUPPORTED, "nq * nprobe too large for one launch");
     const size_t shm = (size_t)M * 256 * sizeof(float) + (size_t)kScanWaves * k * sizeof(uint64_t);
@@ -491,11 +564,11 @@ mk_status launch_scan(const float* term1, const float* term3, const float* cd, c
     const dim3 grid((unsigned)items), block(64 * kScanWaves);
     ProfScope prof("ivf_scan", s);
     switch (queue_regs(k)) {
-        case 1: hipLaunchKernelGGL(ivf_scan<1>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part); break;
-        case 2: hipLaunchKernelGGL(ivf_scan<2>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part); break;
-        case 4: hipLaunchKernelGGL(ivf_scan<4>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part); break;
-        case 8: hipLaunchKernelGGL(ivf_scan<8>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part); break;
-        default: hipLaunchKernelGGL(ivf_scan<16>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part); break;
+        case 1: hipLaunchKernelGGL(ivf_scan<1>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part, work, nq); break;
+        case 2: hipLaunchKernelGGL(ivf_scan<2>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part, work, nq); break;
+        case 4: hipLaunchKernelGGL(ivf_scan<4>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part, work, nq); break;
+        case 8: hipLaunchKernelGGL(ivf_scan<8>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part, work, nq); break;
+        default: hipLaunchKernelGGL(ivf_scan<16>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part, work, nq); break;
     }
     MK_LAUNCHED();
     return MK_OK;
@@ -705,6 +778,102 @@ mk_status search_rerank(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t k, in
     return rerank_keys(keys.as<uint64_t>(), nq, R, xq, xb, ix->d, true, k, D, I, s);
 }
 
+mk_status probe_features(const mk_ivfpq* ix, const float* xq, int64_t nq, float* F,
+                         hipStream_t s) {
+    Scratch cd, ci;
+    MK_TRY(cd.alloc(sizeof(float) * nq * kProbeDists, s));
+    MK_TRY(ci.alloc(sizeof(int64_t) * nq * kProbeDists, s));
+    MK_TRY(knn_search(xq, nq, ix->coarse, ix->coarse_norms, ix->nlist, ix->d, kProbeDists,
+                      MK_METRIC_L2, cd.as<float>(), ci.as<int64_t>(), s));
+    hipLaunchKernelGGL(probe_features_kernel,
+                       dim3(grid_of(nq * (ix->d + kProbeDists))), dim3(kBlock), 0, s, xq, nq,
+                       ix->d, cd.as<float>(), kProbeDists, F);
+    MK_LAUNCHED();
+    return MK_OK;
+}
+
+mk_status probe_labels(const mk_ivfpq* ix, const float* xq, int64_t nq, const int64_t* nn,
+                       int32_t cap, float* target, int32_t* label, hipStream_t s) {
+    Scratch cd, ci, lof;
+    MK_TRY(cd.alloc(sizeof(float) * nq * cap, s));
+    MK_TRY(ci.alloc(sizeof(int64_t) * nq * cap, s));
+    MK_TRY(lof.alloc(sizeof(int32_t) * (ix->ntotal > 0 ? ix->ntotal : 1), s));
+    MK_TRY(knn_search(xq, nq, ix->coarse, ix->coarse_norms, ix->nlist, ix->d, cap, MK_METRIC_L2,
+                      cd.as<float>(), ci.as<int64_t>(), s));
+    hipLaunchKernelGGL(list_of_kernel, dim3(ix->nlist), dim3(kBlock), 0, s, ix->offsets_dev,
+                       ix->nlist, ix->ids, lof.as<int32_t>());
+    MK_LAUNCHED();
+    hipLaunchKernelGGL(probe_labels_kernel, dim3(grid_of(nq)), dim3(kBlock), 0, s,
+                       ci.as<int64_t>(), cap, nq, nn, lof.as<int32_t>(), ix->ntotal, cap, target,
+                       label);
+    MK_LAUNCHED();
+    return MK_OK;
+}
+
+// IVFADC search with a per-query probe count predicted by the network from
+// the query and its coarse distances; R > 0 adds the exact re-rank of an
+// R-entry short list against xb.
+mk_status search_learned(mk_ivfpq* ix, const mk_mlp* net, float delta, const float* xq,
+                         int64_t nq, int32_t k, int32_t cap, int32_t R, const float* xb,
+                         float* D, int64_t* I, int32_t* used, hipStream_t s) {
+    const int32_t M = ix->M;
+    const int32_t kk = R > 0 ? R : k;
+    Scratch cd, ci, F, yhat, tau, cnt, work, tmp, t3, part, keys;
+    MK_TRY(cd.alloc(sizeof(float) * nq * cap, s));
+    MK_TRY(ci.alloc(sizeof(int64_t) * nq * cap, s));
+    MK_TRY(F.alloc(sizeof(float) * nq * (ix->d + kProbeDists), s));
+    MK_TRY(yhat.alloc(sizeof(float) * nq, s));
+    MK_TRY(tau.alloc(sizeof(int32_t) * nq, s));
+    MK_TRY(cnt.alloc(sizeof(int64_t) * nq, s));
+    MK_TRY(work.alloc(sizeof(int64_t) * (nq + 1), s));
+    // coarse order up to cap probes; its first kProbeDists distances are the
+    // network's distance features
+    MK_TRY(knn_search(xq, nq, ix->coarse, ix->coarse_norms, ix->nlist, ix->d, cap, MK_METRIC_L2,
+                      cd.as<float>(), ci.as<int64_t>(), s));
+    hipLaunchKernelGGL(probe_features_kernel,
+                       dim3(grid_of(nq * (ix->d + kProbeDists))), dim3(kBlock), 0, s, xq, nq,
+                       ix->d, cd.as<float>(), cap, F.as<float>());
+    MK_LAUNCHED();
+    MK_TRY(mlp_forward_dev(net, F.as<float>(), nq, yhat.as<float>(), s));
+    hipLaunchKernelGGL(probe_count_kernel, dim3(grid_of(nq)), dim3(kBlock), 0, s,
+                       yhat.as<float>(), nq, delta, cap, tau.as<int32_t>(), cnt.as<int64_t>());
+    MK_LAUNCHED();
+    if (used)
+        MK_HIP(hipMemcpyAsync(used, tau.ptr, sizeof(int32_t) * nq, hipMemcpyDeviceToDevice, s));
+    // work[0] = 0, work[q + 1] = tau[0] + ... + tau[q]
+    MK_HIP(hipMemsetAsync(work.ptr, 0, sizeof(int64_t), s));
+    size_t tmp_bytes = 0;
+    MK_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, cnt.as<int64_t>(),
+                                            work.as<int64_t>() + 1, (int)nq, s));
+    MK_TRY(tmp.alloc(tmp_bytes, s));
+    MK_HIP(hipcub::DeviceScan::InclusiveSum(tmp.ptr, tmp_bytes, cnt.as<int64_t>(),
+                                            work.as<int64_t>() + 1, (int)nq, s));
+    int64_t nwork = 0;
+    MK_HIP(hipMemcpyAsync(&nwork, work.as<int64_t>() + nq, sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+    MK_HIP(hipStreamSynchronize(s));
+    MK_TRY(t3.alloc(sizeof(float) * nq * M * 256, s));
+    MK_TRY(part.alloc(sizeof(uint64_t) * nwork * kk, s));
+    hipLaunchKernelGGL(term3_kernel, dim3(grid_of(nq * M * 256)), dim3(kBlock), 0, s, xq, nq, M,
+                       ix->dsub, ix->books, t3.as<float>());
+    MK_LAUNCHED();
+    MK_TRY(launch_scan(ix->term1, t3.as<float>(), cd.as<float>(), ci.as<int64_t>(),
+                       ix->offsets_dev, ix->codes, ix->ids, M, nq, cap, kk, part.as<uint64_t>(),
+                       s, work.as<int64_t>(), nwork));
+    if (R <= 0) {
+        ProfScope prof("ivf_merge", s);
+        return merge_key_lists(part.as<uint64_t>(), nq, 0, k, D, I, s, nullptr,
+                               work.as<int64_t>());
+    }
+    MK_TRY(keys.alloc(sizeof(uint64_t) * nq * 64 * queue_regs(R), s));
+    {
+        ProfScope prof("ivf_merge", s);
+        MK_TRY(merge_key_lists(part.as<uint64_t>(), nq, 0, R, nullptr, nullptr, s,
+                               keys.as<uint64_t>(), work.as<int64_t>()));
+    }
+    return rerank_keys(keys.as<uint64_t>(), nq, R, xq, xb, ix->d, true, k, D, I, s);
+}
+
 }  // namespace
 
 }  // namespace mk
@@ -825,6 +994,74 @@ extern "C" mk_status mk_ivfpq_search_rerank(mk_ivfpq* ix, const float* xq, int64
     MK_REQUIRE(xq && D && I && (xb || nb == 0), MK_ERR_INVALID_ARG, "null pointer");
     return mk::search_rerank(ix, xq, nq, k, nprobe, R, xb, D, I,
                              static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_ivfpq_probe_features(const mk_ivfpq* ix, const float* xq, int64_t nq,
+                                             float* F, mk_stream_t stream) {
+    MK_REQUIRE(ix, MK_ERR_INVALID_ARG, "null index");
+    MK_REQUIRE(ix->trained, MK_ERR_STATE, "index is not trained");
+    MK_REQUIRE(ix->nlist >= mk::kProbeDists, MK_ERR_UNSUPPORTED, "needs nlist >= 32");
+    MK_REQUIRE(nq >= 0, MK_ERR_INVALID_ARG, "nq must be >= 0");
+    if (nq == 0) return MK_OK;
+    MK_REQUIRE(xq && F, MK_ERR_INVALID_ARG, "null pointer");
+    return mk::probe_features(ix, xq, nq, F, static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_ivfpq_probe_labels(const mk_ivfpq* ix, const float* xq, int64_t nq,
+                                           const int64_t* nn_ids, int32_t cap, float* target,
+                                           int32_t* label, mk_stream_t stream) {
+    MK_REQUIRE(ix, MK_ERR_INVALID_ARG, "null index");
+    MK_REQUIRE(ix->trained, MK_ERR_STATE, "index is not trained");
+    MK_REQUIRE(nq >= 0, MK_ERR_INVALID_ARG, "nq must be >= 0");
+    MK_REQUIRE(cap >= 1 && cap <= ix->nlist && cap <= mk::kMaxK, MK_ERR_INVALID_ARG,
+               "need 1 <= cap <= min(nlist, 1024)");
+    if (nq == 0) return MK_OK;
+    MK_REQUIRE(xq && nn_ids && target, MK_ERR_INVALID_ARG, "null pointer");
+    return mk::probe_labels(ix, xq, nq, nn_ids, cap, target, label,
+                            static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_ivfpq_search_learned(mk_ivfpq* ix, const mk_mlp* net, float delta,
+                                             const float* xq, int64_t nq, int32_t k, int32_t cap,
+                                             int32_t R, const float* xb, int64_t nb, float* D,
+                                             int64_t* I, int32_t* nprobe_used,
+                                             mk_stream_t stream) {
+    MK_REQUIRE(ix && net, MK_ERR_INVALID_ARG, "null index or network");
+    MK_REQUIRE(ix->trained, MK_ERR_STATE, "index is not trained");
+    MK_REQUIRE(mk::mlp_inputs(net) == ix->d + mk::kProbeDists, MK_ERR_INVALID_ARG,
+               "network inputs must be d + 32");
+    MK_REQUIRE(nq >= 0, MK_ERR_INVALID_ARG, "nq must be >= 0");
+    MK_REQUIRE(k >= 1, MK_ERR_INVALID_ARG, "k must be >= 1");
+    MK_REQUIRE(k <= mk::kMaxK && R <= mk::kMaxK, MK_ERR_UNSUPPORTED, "k and R must be <= 1024");
+    MK_REQUIRE(cap >= mk::kProbeDists && cap <= ix->nlist && cap <= mk::kMaxK,
+               MK_ERR_INVALID_ARG, "need 32 <= cap <= min(nlist, 1024)");
+    MK_REQUIRE(R <= 0 || R >= k, MK_ERR_INVALID_ARG, "need R >= k for the re-rank");
+    MK_REQUIRE(R <= 0 || (xb && nb >= ix->ntotal), MK_ERR_INVALID_ARG,
+               "the re-rank needs a database row for every added id");
+    if (nq == 0) return MK_OK;
+    MK_REQUIRE(xq && D && I, MK_ERR_INVALID_ARG, "null pointer");
+    return mk::search_learned(ix, net, delta, xq, nq, k, cap, R, xb, D, I, nprobe_used,
+                              static_cast<hipStream_t>(stream));
+}
+
+extern "C" int32_t mk_ivfpq_dim(const mk_ivfpq* ix) { return ix ? ix->d : 0; }
+
+extern "C" mk_status mk_ivfpq_search_workspace_bytes(const mk_ivfpq* ix, int64_t nq, int32_t k,
+                                                     int32_t nprobe, int32_t R, size_t* bytes) {
+    MK_REQUIRE(ix && bytes, MK_ERR_INVALID_ARG, "null pointer");
+    MK_REQUIRE(nq >= 0 && k >= 1 && nprobe >= 1, MK_ERR_INVALID_ARG, "bad sizes");
+    const int64_t kk = R > 0 ? R : k;
+    const int64_t qn = nq;
+    // coarse search: results, and at most nlist / (32 * queue) chunk lists
+    const int64_t ks = 64 * (int64_t)mk::queue_regs(std::min(nprobe + 16, mk::kMaxK));
+    const int64_t chunks = std::max<int64_t>(1, ix->nlist / (32 * ks));
+    int64_t b = qn * nprobe * (4 + 8) + qn * chunks * ks * 8 + qn * 4;
+    b += qn * (int64_t)ix->M * 256 * 4;      // term-3 tables
+    b += qn * nprobe * kk * 8;                // per-list partial results
+    if (R > 0) b += qn * 64 * (int64_t)mk::queue_regs(R) * 8;  // short lists
+    b += qn * (ix->d + mk::kProbeDists) * 4 + qn * 16;          // learned-count features
+    *bytes = (size_t)b;
+    return MK_OK;
 }
 
 extern "C" mk_status mk_ivfpq_get_quantizers(const mk_ivfpq* ix, float* coarse, float* codebooks) {

@@ -63,13 +63,15 @@ mk_status knn_launch(const float* xq, int64_t nq, const float* xb, const float* 
     int64_t nqb, nchunks, chunk_len;
     plan_chunks(nq, nb, S::BQ, S::BN, KS, &nqb, &nchunks, &chunk_len);
 
-    Scratch part;
+    Scratch part, bound;
     mk_status st = part.alloc(sizeof(uint64_t) * (size_t)nq * (size_t)nchunks * KS, stream);
     if (st != MK_OK) return st;
+    MK_TRY(bound.alloc(sizeof(uint32_t) * (size_t)nq, stream));
+    MK_TRY(clear_bounds(bound.as<uint32_t>(), nq, stream));
     const int64_t nblocks = nqb * nchunks;
     MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
     FusedArgs a{xq, xb, yn, nullptr, nullptr, nq, nb, d, d, chunk_len, (int32_t)nchunks,
-                (int32_t)nqb, keff, part.as<uint64_t>()};
+                (int32_t)nqb, keff, part.as<uint64_t>(), bound.as<uint32_t>()};
     {
         ProfScope prof("knn_fused", stream);
         auto kern = vec ? (l2 ? knn_fused<OpF32, KR, DP, true, true> : knn_fused<OpF32, KR, DP, true, false>)

@@ -84,14 +84,16 @@ mk_status lowp_launch(const float* xq, const void* xq_lp, const float* xq_inv, i
     constexpr int KS = 64 * KR;
     int64_t nqb, nchunks, chunk_len;
     plan_chunks(nq, nb, S::BQ, S::BN, KS, &nqb, &nchunks, &chunk_len);
-    Scratch part;
+    Scratch part, bound;
     mk_status st = part.alloc(sizeof(uint64_t) * (size_t)nq * (size_t)nchunks * KS, stream);
     if (st != MK_OK) return st;
+    MK_TRY(bound.alloc(sizeof(uint32_t) * (size_t)nq, stream));
+    MK_TRY(clear_bounds(bound.as<uint32_t>(), nq, stream));
     const int64_t nblocks = nqb * nchunks;
     MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
     const int32_t ld = lowp_stride(d);
     FusedArgs a{xq_lp, xb_lp, yn, xq_inv, xb_inv, nq, nb, ld, ld, chunk_len, (int32_t)nchunks,
-                (int32_t)nqb, R, part.as<uint64_t>()};
+                (int32_t)nqb, R, part.as<uint64_t>(), bound.as<uint32_t>()};
     {
         ProfScope prof(Op::SCALED ? "knn_fused_fp8" : "knn_fused_bf16", stream);
         auto kern = l2 ? knn_fused<Op, KR, DP, true, true> : knn_fused<Op, KR, DP, true, false>;

@@ -128,18 +128,22 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_pass1(
     }
 }
 
-// Pass 2: per row, select the k best of nseg * k partial keys, written as
+// Pass 2: per row, select the k best of nseg * k partial keys (or, with
+// seg_offs, of the lists seg_offs[row] .. seg_offs[row + 1] - 1), written as
 // (value, index) pairs or, with keys_out, as the 64*KR-entry sorted key list.
 template <int KR, int T, bool LARGEST>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_merge(
     const uint64_t* __restrict__ partial, int64_t nrows, int32_t nseg, int32_t k,
-    float* __restrict__ vals, int64_t* __restrict__ idx, uint64_t* __restrict__ keys_out) {
+    float* __restrict__ vals, int64_t* __restrict__ idx, uint64_t* __restrict__ keys_out,
+    const int64_t* __restrict__ seg_offs) {
     const int wave = threadIdx.x / 64;
     const int lane = lane_id();
     const int64_t row = (int64_t)blockIdx.x * kWavesPerBlock + wave;
     if (row >= nrows) return;
-    const uint64_t* p = partial + row * (int64_t)nseg * k;
-    const int64_t n = (int64_t)nseg * k;
+    const int64_t s0 = seg_offs ? seg_offs[row] : row * (int64_t)nseg;
+    const int64_t s1 = seg_offs ? seg_offs[row + 1] : s0 + nseg;
+    const uint64_t* p = partial + s0 * k;
+    const int64_t n = (s1 - s0) * k;
     WaveSelect<KR, T> ws;
     ws.init(k);
 #pragma unroll 1
@@ -187,7 +191,7 @@ mk_status kselect_launch(const float* a, int64_t nrows, int64_t len, int32_t k, 
         hipLaunchKernelGGL((kselect_merge<KR, T, LARGEST>),
                            dim3((unsigned)ceil_div(nrows, kWavesPerBlock)), dim3(64 * kWavesPerBlock),
                            0, stream, part.as<uint64_t>(), nrows, (int32_t)nseg, k, vals, idx,
-                           (uint64_t*)nullptr);
+                           (uint64_t*)nullptr, (const int64_t*)nullptr);
         MK_LAUNCHED();
     }
     return MK_OK;
@@ -208,20 +212,21 @@ mk_status kselect_dispatch(const float* a, int64_t nrows, int64_t len, int32_t k
 }  // namespace
 
 mk_status merge_key_lists(const uint64_t* partial, int64_t nrows, int32_t nseg, int32_t k,
-                          float* vals, int64_t* idx, hipStream_t s, uint64_t* keys_out) {
+                          float* vals, int64_t* idx, hipStream_t s, uint64_t* keys_out,
+                          const int64_t* seg_offs) {
     if (nrows == 0) return MK_OK;
     const dim3 grid((unsigned)ceil_div(nrows, kWavesPerBlock)), block(64 * kWavesPerBlock);
     switch (queue_regs(k)) {
         case 1: hipLaunchKernelGGL((kselect_merge<1, SelParams<1>::T, false>), grid, block, 0, s,
-                                   partial, nrows, nseg, k, vals, idx, keys_out); break;
+                                   partial, nrows, nseg, k, vals, idx, keys_out, seg_offs); break;
         case 2: hipLaunchKernelGGL((kselect_merge<2, SelParams<2>::T, false>), grid, block, 0, s,
-                                   partial, nrows, nseg, k, vals, idx, keys_out); break;
+                                   partial, nrows, nseg, k, vals, idx, keys_out, seg_offs); break;
         case 4: hipLaunchKernelGGL((kselect_merge<4, SelParams<4>::T, false>), grid, block, 0, s,
-                                   partial, nrows, nseg, k, vals, idx, keys_out); break;
+                                   partial, nrows, nseg, k, vals, idx, keys_out, seg_offs); break;
         case 8: hipLaunchKernelGGL((kselect_merge<8, SelParams<8>::T, false>), grid, block, 0, s,
-                                   partial, nrows, nseg, k, vals, idx, keys_out); break;
+                                   partial, nrows, nseg, k, vals, idx, keys_out, seg_offs); break;
         default: hipLaunchKernelGGL((kselect_merge<16, SelParams<16>::T, false>), grid, block, 0,
-                                    s, partial, nrows, nseg, k, vals, idx, keys_out); break;
+                                    s, partial, nrows, nseg, k, vals, idx, keys_out, seg_offs); break;
     }
     MK_LAUNCHED();
     return MK_OK;

@@ -139,4 +139,26 @@ def ivfpq_workload(nb: int = 10_000_000, nq: int = 10_000, nt: int = 500_000):
     return {"xb": xb, "xq": xq, "sample": sample, "nlist": 4096, "M": 16,
             "coarse_init": choose_rows(nt, 4096, (103, 3)),
             "pq_init": pq_init_rows(nt, 16, (103, 4)), "k": 100,
-            "nprobes": (1, 8, 16, 32, 64, 128), "rerank": (256, 1024)}
+            "nprobes": (1, 8, 16, 32, 64, 128), "rerank": (256, 1024),
+            "learn_rerank": 256, "learn_cap": 256, "learn_fixed_nprobes": tuple(range(1, 13)),
+            "learn_train": 200_000, "learn_epochs": 10, "serve_requests": 2000,
+            "serve_load": (0.5, 0.8)}
+
+
+def mlp_init(din: int, hidden: int, seed) -> np.ndarray:
+    """He-uniform initial parameters of the probe-count network, flat float32
+    in the order W1 [hidden, din], b1, W2 [hidden, hidden], b2, w3, b3:
+    weights U(-sqrt(6 / fan_in), +sqrt(6 / fan_in)), biases zero."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed if isinstance(seed, tuple) else (seed,)))
+    w1 = rng.uniform(-1, 1, (hidden, din)) * np.sqrt(6.0 / din)
+    w2 = rng.uniform(-1, 1, (hidden, hidden)) * np.sqrt(6.0 / hidden)
+    w3 = rng.uniform(-1, 1, hidden) * np.sqrt(6.0 / hidden)
+    z = np.zeros(hidden)
+    return np.concatenate([w1.ravel(), z, w2.ravel(), z, w3, [0.0]]).astype(np.float32)
+
+
+def permutation(n: int, seed) -> np.ndarray:
+    """Seeded permutation of 0 .. n-1 (int64), e.g. the row order of a
+    training epoch."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed if isinstance(seed, tuple) else (seed,)))
+    return rng.permutation(n).astype(np.int64)

@@ -1,0 +1,278 @@
+"""Learned probe count on the GPU (through the C ABI) against the float64
+oracle in oracle/mlp.py: standardisation, forward pass, gradient (FP32 within
+1e-4, BF16 within 2e-2 relative in norm, the oracle using the same
+BF16-rounded weights and inputs), Adam steps, features, labels and the
+search with a per-query probe count."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+from paper_1702_08734_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+DIN, H = 160, 256
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_08734_amd import api as a
+    a.lib()
+    return a
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _net(api, prec, seed=1):
+    net = api.MLP(DIN, H, prec)
+    theta = synth.mlp_init(DIN, H, seed)
+    # non-zero biases exercise every bias path
+    rng = np.random.default_rng(seed)
+    theta = theta.copy()
+    o = H * DIN
+    theta[o:o + H] = rng.uniform(-0.1, 0.1, H)
+    o += H + H * H
+    theta[o:o + H] = rng.uniform(-0.1, 0.1, H)
+    theta[-1] = 0.3
+    net.set_params(theta)
+    return net, theta
+
+
+def _features(n, seed):
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal((n, DIN)).astype(np.float32) * 3 + 1
+    return F
+
+
+def _standardized(net, F):
+    mean, inv = net.get_standardization()
+    return ((F - mean) * inv).astype(np.float32)  # same float32 operations as the kernel
+
+
+def _oracle_theta(theta, prec):
+    th = theta.astype(np.float64).copy()
+    if prec == "bf16":  # the matrix-core operands: W1 and W2
+        n1 = H * DIN
+        th[:n1] = omlp.bf16_round(theta[:n1])
+        o = n1 + H
+        th[o:o + H * H] = omlp.bf16_round(theta[o:o + H * H])
+    return th
+
+
+def test_standardization_matches_oracle(api):
+    net = api.MLP(DIN, H)
+    F = _features(3000, 2)
+    F[:, 5] = 1.25  # a constant column
+    net.fit_standardization(dev(F))
+    mean, inv = net.get_standardization()
+    m_o, s_o = omlp.standardization(F)
+    np.testing.assert_allclose(mean, m_o, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(inv, 1.0 / s_o, rtol=1e-6)
+    assert inv[5] == 1.0
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 2e-2)])
+@pytest.mark.parametrize("B", [1, 300, 1024])
+def test_gradient_matches_oracle(api, prec, tol, B):
+    say(f"mlp gradient {prec} B={B}")
+    net, theta = _net(api, prec)
+    F = _features(1500, 3)
+    net.fit_standardization(dev(F))
+    rows = synth.permutation(1500, 4)[:B]
+    y = np.random.default_rng(5).uniform(0, 8, 1500).astype(np.float32)
+    loss = net.loss_grad(dev(F), dev(y), dev(rows))
+    _, g = net.get_params()
+    Xs = _standardized(net, F)[rows]
+    if prec == "bf16":
+        Xs = omlp.bf16_round(Xs)
+    lo, go = omlp.loss_and_grad(_oracle_theta(theta, prec), Xs, y[rows], DIN, H)
+    err = np.linalg.norm(g.astype(np.float64) - go) / np.linalg.norm(go)
+    say(f"  relative gradient error {err:.2e}, loss {loss.item():.6f} vs {lo:.6f}")
+    assert err <= tol
+    assert abs(loss.item() - lo) <= tol * lo
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
+def test_forward_matches_oracle(api, prec, tol):
+    net, theta = _net(api, prec, seed=7)
+    F = _features(777, 8)
+    net.fit_standardization(dev(F))
+    yg = net.forward(dev(F)).cpu().numpy().astype(np.float64)
+    Xs = _standardized(net, F)
+    if prec == "bf16":
+        Xs = omlp.bf16_round(Xs)
+    *_, yo = omlp.forward(_oracle_theta(theta, prec), Xs, DIN, H)
+    err = np.linalg.norm(yg - yo) / np.linalg.norm(yo)
+    assert err <= tol, err
+
+
+def test_identity_network_is_relu(api):
+    # W1 = [I 0], W2 = I, zero biases, w3 = e_j: the output is relu(x_j)
+    net = api.MLP(DIN, H)
+    xs = np.random.default_rng(1).standard_normal((100, DIN)).astype(np.float32)
+    for j in (0, 17, 159):
+        W1 = np.zeros((H, DIN), np.float32)
+        W1[:DIN, :DIN] = np.eye(DIN)
+        w3 = np.zeros(H, np.float32)
+        w3[j] = 1.0
+        theta = np.concatenate([W1.ravel(), np.zeros(H), np.eye(H).ravel(), np.zeros(H), w3,
+                                [0.0]]).astype(np.float32)
+        net.set_params(theta)
+        y = net.forward(dev(xs)).cpu().numpy()  # identity standardisation
+        np.testing.assert_array_equal(y, np.maximum(xs[:, j], 0))
+
+
+def test_train_epoch_matches_oracle_adam(api):
+    say("mlp train epoch vs oracle Adam")
+    net, theta = _net(api, "fp32", seed=11)
+    n, batch, lr = 700, 256, 1e-3
+    F = _features(n, 12)
+    net.fit_standardization(dev(F))
+    y = np.random.default_rng(13).uniform(0, 8, n).astype(np.float32)
+    perm = synth.permutation(n, 14)
+    losses = net.train_epoch(dev(F), dev(y), dev(perm), batch, lr).cpu().numpy()
+    th_g, _ = net.get_params()
+    Xs = _standardized(net, F)
+    th = theta.astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    gmax = 0.0
+    small = np.zeros(len(th), bool)
+    for b, off in enumerate(range(0, n, batch)):
+        rows = perm[off:off + batch]
+        lo, go = omlp.loss_and_grad(th, Xs[rows], y[rows], DIN, H)
+        assert abs(losses[b] - lo) <= 1e-4 * lo
+        gmax = max(gmax, np.abs(go).max())
+        small |= np.abs(go) < 1e-3 * np.abs(go).max()
+        th, m, v = omlp.adam_step(th, go, m, v, b + 1, lr=lr)
+    # Adam moves every weight by about lr per step whatever the gradient's
+    # size, so weights whose gradient is tiny are only held to 2 lr per step
+    diff = np.abs(th_g.astype(np.float64) - th)
+    nb = (n + batch - 1) // batch
+    assert np.all(diff[~small] <= 1e-5 + 1e-3 * np.abs(th[~small]))
+    assert np.all(diff[small] <= 2 * lr * nb + 1e-6)
+
+
+def test_training_reduces_loss(api):
+    net, _ = _net(api, "bf16", seed=21)
+    n = 4096
+    rng = np.random.default_rng(22)
+    F = rng.standard_normal((n, DIN)).astype(np.float32)
+    y = (np.abs(F[:, :4]).sum(1) + 0.5 * F[:, 10]).astype(np.float32)
+    net.fit_standardization(dev(F))
+    first = last = None
+    for ep in range(8):
+        losses = net.train_epoch(dev(F), dev(y), dev(synth.permutation(n, (23, ep))), 256,
+                                 1e-3).cpu().numpy()
+        first = losses[0] if first is None else first
+        last = losses[-4:].mean()
+    say(f"training loss {first:.4f} -> {last:.4f}")
+    assert last < 0.2 * first
+
+
+# ------------------------------------------------------------ with an index
+@pytest.fixture(scope="module")
+def index(api):
+    say("build IVFPQ index for the probe-count tests")
+    mix = synth.Mixture(100, 128, (31, 0))
+    xt = mix.sample(20000, (31, 1))
+    xb = mix.sample(50000, (31, 2))
+    xq = mix.sample(200, (31, 3))
+    nlist, M = 64, 16
+    ix = api.IVFPQ(128, nlist, M)
+    ix.train(dev(xt), 6, synth.choose_rows(len(xt), nlist, 5), synth.pq_init_rows(len(xt), M, 6))
+    ix.add(dev(xb))
+    return {"ix": ix, "xb": xb, "xq": xq}
+
+
+def test_probe_features_and_labels(api, index):
+    ix, xb, xq = index["ix"], index["xb"], index["xq"]
+    coarse, _ = ix.get_quantizers()
+    F = ix.probe_features(dev(xq)).cpu().numpy()
+    np.testing.assert_array_equal(F[:, :128], xq)
+    cd = ((xq.astype(np.float64)[:, None, :] - coarse.astype(np.float64)[None]) ** 2).sum(2)
+    Fo = omlp.features(xq, cd)
+    scale = 1e-3 * ((xq.astype(np.float64) ** 2).sum(1)[:, None] + cd.max())
+    assert np.all(np.abs(F[:, 128:] - Fo[:, 128:]) <= 1e-5 * np.maximum(Fo[:, 128:], scale))
+    # labels from the exact nearest neighbours
+    _, nn = oracle.knn(xq, xb, 1)
+    target, label = ix.probe_labels(dev(xq), dev(nn[:, 0]), 48)
+    label = label.cpu().numpy()
+    offs, _, ids = ix.get_lists()
+    list_of = np.empty(len(ids), np.int64)
+    list_of[ids] = np.repeat(np.arange(len(coarse)), np.diff(offs))
+    order = np.argsort(cd, axis=1, kind="stable")
+    lo = omlp.labels(list_of[nn[:, 0]], order, 48)
+    srt = np.sort(cd, 1)
+    for j in range(len(xq)):
+        r = lo[j]
+        if label[j] != r:  # only where the coarse order is band-ambiguous
+            a, b = sorted((label[j], r))
+            assert srt[j, b - 1] - srt[j, a - 1] <= 1e-5 * srt[j, b - 1], (j, label[j], r)
+    np.testing.assert_allclose(target.cpu().numpy(), np.log2(label), rtol=1e-6)
+
+
+@pytest.mark.parametrize("R", [0, 200])
+def test_constant_network_equals_fixed_probe(api, index, R):
+    # zero weights: the prediction is b3 everywhere, so every query probes
+    # the same count and the result is the fixed-nprobe search's, bit for bit
+    ix, xb, xq = index["ix"], index["xb"], index["xq"]
+    net = api.MLP(128 + 32, H)
+    theta = np.zeros(net.n_params, np.float32)
+    theta[-1] = np.log2(6.0) - 0.01  # 2^(b3) = 5.97 -> 6 probes
+    net.set_params(theta)
+    k = 10
+    D, I, tau = ix.search_learned(net, 0.0, dev(xq), k, 48, R, dev(xb) if R else None)
+    assert np.all(tau.cpu().numpy() == 6)
+    if R:
+        Df, If = ix.search_rerank(dev(xq), k, 6, R, dev(xb))
+    else:
+        Df, If = ix.search(dev(xq), k, 6)
+    np.testing.assert_array_equal(I.cpu().numpy(), If.cpu().numpy())
+    np.testing.assert_array_equal(D.cpu().numpy(), Df.cpu().numpy())
+    # delta shifts the count: 2^(log2 6 - 0.01 + 1) -> 12
+    _, _, tau2 = ix.search_learned(net, 1.0, dev(xq), k, 48)
+    assert np.all(tau2.cpu().numpy() == 12)
+
+
+def test_learned_search_matches_oracle(api, index):
+    say("learned-probe search vs oracle")
+    ix, xb, xq = index["ix"], index["xb"], index["xq"]
+    net = api.MLP(128 + 32, H)
+    theta = synth.mlp_init(160, H, 41)
+    theta[-1] = 2.5
+    net.set_params(theta)
+    F = ix.probe_features(dev(xq))
+    net.fit_standardization(F)
+    k, cap = 20, 48
+    D, I, tau = ix.search_learned(net, 0.0, dev(xq), k, cap)
+    tau = tau.cpu().numpy()
+    yhat = net.forward(F).cpu().numpy()
+    to = omlp.probe_count(yhat, 0.0, cap)
+    near = np.abs(2.0 ** yhat.astype(np.float64) - np.round(2.0 ** yhat.astype(np.float64))) < 1e-4
+    assert np.all((tau == to) | near)
+    assert len(set(tau.tolist())) > 3  # the counts really vary per query
+    coarse, books = ix.get_quantizers()
+    offs, codes, ids = ix.get_lists()
+    from test_gpu_ivfpq import check_ivf
+    Dg, Ig = D.cpu().numpy(), I.cpu().numpy()
+    bad = 0
+    for j in range(len(xq)):
+        # per query: the probe set is the tau_j nearest lists (Eq. 5)
+        fails, _ = check_ivf(Dg[j:j + 1], Ig[j:j + 1], xq, np.array([j]), coarse, books,
+                               offs, codes, ids, k, int(tau[j]))
+        bad += len(fails)
+    assert bad == 0
