@@ -100,14 +100,77 @@ def _timed(torch, fn, reps):
 
 
 def kselect_section(api, synth, torch):
+    """Row-wise k-selection of 10,000 U[0,1) rows of length l (HBM-bound)."""
     progress("kselect: generating 10,000 x 128,000 rows")
-    a = torch.from_numpy(synth.kselect_rows(10_000, 128_000)).cuda()
-    res = {"rows": 10_000, "len": 128_000, "input_gb": a.numel() * 4 / 1e9}
-    for k in (100, 1000):
-        dt = _timed(torch, lambda: api.kselect(a, k), 3)
-        gbs = (a.numel() * 4 + a.shape[0] * k * 12) / dt / 1e9
-        res[f"k{k}"] = {"ms": round(dt * 1e3, 3), "GB/s": round(gbs, 1),
-                        "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    full = torch.from_numpy(synth.kselect_rows(10_000, 128_000)).cuda()
+    res = {"rows": 10_000, "lengths": {}}
+    for length in (1_000, 8_000, 32_000, 128_000):
+        a = full[:, :length].contiguous() if length < full.shape[1] else full
+        row = {"input_gb": round(a.numel() * 4 / 1e9, 3)}
+        for k in (100, 1000):
+            if k > length:
+                continue
+            dt = _timed(torch, lambda: api.kselect(a, k), 3)
+            gbs = (a.numel() * 4 + a.shape[0] * k * 12) / dt / 1e9
+            row[f"k{k}"] = {"ms": round(dt * 1e3, 3), "GB/s": round(gbs, 1),
+                            "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+        res["lengths"][str(length)] = row
+        del a
+    return res
+
+
+def small_exact_section(api, synth, torch):
+    """Latency of one exact search on the 50,000 x 64 N(0,1) database with
+    500 queries, k = 10 (launch-bound: 3.2 GFLOP)."""
+    w = synth.exact_small()
+    xb = torch.from_numpy(w["xb"]).cuda()
+    xq = torch.from_numpy(w["xq"]).cuda()
+    dt = _timed(torch, lambda: api.knn_search(xq, xb, w["k"]), 20)
+    return {"workload": "50,000 x 64 N(0,1), 500 queries, k = 10, L2",
+            "latency_ms": round(dt * 1e3, 3),
+            "TFLOP/s": round(2 * 500 * 50_000 * 64 / dt / 1e12, 2)}
+
+
+def lowp_section(api, synth, torch):
+    """BF16 / FP8-E4M3 brute force on the matrix cores with an exact FP32
+    re-rank of the R = 4k best against FP32 brute force: 20,000,000 x 96
+    unit-norm rows of a 2,000-component mixture, 10,000 queries, k = 100."""
+    import numpy as np
+    w = synth.lowp_workload()
+    progress("lowp: generating 20,000,000 x 96 unit-norm mixture")
+    xb = torch.from_numpy(w["xb"]).cuda()
+    xq = torch.from_numpy(w["xq"]).cuda()
+    k, R = w["k"], w["R"]
+    nq, nb, d = xq.shape[0], xb.shape[0], xb.shape[1]
+    flop = 2.0 * nq * nb * d
+    res = {"workload": "20,000,000 x 96 unit-norm 2,000-component mixture, 10,000 queries, "
+                       f"k = {k}, re-rank R = {R}", "metrics": {}}
+    for metric in w["metrics"]:
+        progress(f"lowp: fp32 {metric}")
+        t0 = time.perf_counter()
+        De, Ie = api.knn_search(xq, xb, k, metric)
+        torch.cuda.synchronize()
+        t_fp32 = time.perf_counter() - t0
+        Ie = Ie.cpu().numpy()
+        row = {"fp32": {"ms": round(t_fp32 * 1e3, 1), "TFLOP/s": round(flop / t_fp32 / 1e12, 2)}}
+        for prec in ("bf16", "fp8"):
+            progress(f"lowp: {prec} {metric}")
+            lp, inv = api.quantize_rows(xb, prec)
+            api.knn_search_lowp(xq, xb, lp, inv, k, R, prec, metric)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            D, I = api.knn_search_lowp(xq, xb, lp, inv, k, R, prec, metric)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            I = I.cpu().numpy()
+            rec = float(np.mean([len(set(I[j]) & set(Ie[j])) / k for j in range(nq)]))
+            # distances are the exact FP32 direct form of the returned rows
+            row[prec] = {"ms": round(dt * 1e3, 1), "TFLOP/s": round(flop / dt / 1e12, 2),
+                         "speedup_vs_fp32": round(t_fp32 / dt, 2),
+                         "recall_at_100_vs_fp32_exact": round(rec, 4)}
+            del lp, inv
+            torch.cuda.empty_cache()
+        res["metrics"][metric] = row
     return res
 
 
@@ -428,7 +491,8 @@ def main() -> int:
     del xq, xb
     torch.cuda.empty_cache()
     if not args.skip_extra:
-        for name, fn in (("kselect", kselect_section), ("ivfpq", ivfpq_section)):
+        for name, fn in (("small_exact", small_exact_section), ("kselect", kselect_section),
+                         ("ivfpq", ivfpq_section), ("lowp", lowp_section)):
             try:
                 out["extra"][name] = fn(api, synth, torch)
             except Exception as e:  # the headline value stands on its own

@@ -34,6 +34,7 @@ struct MultiSelect {
     vq kl, kh;           // key of each query's current k-th entry (wave-uniform)
     vqf kf;              // its score, or the bound below if that is smaller
     vqf bd;              // score bound from other database chunks
+    int cnt[QW];         // keys in each query's thread-queue buffer
     int keff;
 
     __device__ __forceinline__ void init(int k_eff) {
@@ -45,6 +46,8 @@ struct MultiSelect {
         kl = kh = ~0u;
         kf = INFINITY;
         bd = INFINITY;
+#pragma unroll
+        for (int q = 0; q < QW; ++q) cnt[q] = 0;
     }
 
     // Candidates scoring above b cannot enter query q's result (another
@@ -77,6 +80,8 @@ struct MultiSelect {
             tl[i][q] = ~0u;
             th[i][q] = ~0u;
         }
+#pragma unroll
+        for (int qq = 0; qq < QW; ++qq) cnt[qq] = qq == q ? 0 : cnt[qq];
         kl[q] = (uint32_t)kk;
         kh[q] = (uint32_t)(kk >> 32);
         kf[q] = fminf(kk == kSentinel ? INFINITY : key_score(kk), bd[q]);
@@ -93,17 +98,18 @@ struct MultiSelect {
                 const uint64_t key = ok ? make_key(score[q], idx) : kSentinel;
                 const uint64_t kth = ((uint64_t)kh[q] << 32) | kl[q];
                 const bool take = key < kth;
-                if (__any(take)) {
+                const uint64_t bal = __ballot(take);
+                if (bal) {
                     uint64_t tq[T];
 #pragma unroll
                     for (int i = 0; i < T; ++i) tq[i] = ((uint64_t)th[i][q] << 32) | tl[i][q];
-                    tq_push<T>(tq, key, take);
+                    cnt[q] = tq_append<T>(tq, key, take, bal, cnt[q]);
 #pragma unroll
                     for (int i = 0; i < T; ++i) {
                         tl[i][q] = (uint32_t)tq[i];
                         th[i][q] = (uint32_t)(tq[i] >> 32);
                     }
-                    if (__any(tq_full<T>(tq))) full |= 1u << q;
+                    if (cnt[q] > 64 * (T - 1)) full |= 1u << q;
                 }
             }
         }
@@ -189,6 +195,14 @@ __device__ __forceinline__ int64_t xcd_logical_id(int64_t bid, int64_t nblocks) 
     const int64_t x = bid & 7, pos = bid >> 3;
     const int64_t base = nblocks >> 3, rem = nblocks & 7;
     return x * base + (x < rem ? x : rem) + pos;
+}
+
+// s_waitcnt immediate (gfx9 encoding) that waits until at most N vector
+// memory operations are outstanding and for all LDS operations.
+template <int N>
+constexpr int waitcnt_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt is 6 bits");
+    return (N & 0xF) | (0x7 << 4) | (0x0 << 8) | (((N >> 4) & 0x3) << 14);
 }
 
 // Workgroup of the fused kernel: 4 producer waves (one per SIMD) compute the
@@ -285,7 +299,13 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
     constexpr int SK0 = 4 / (QPB * DPB) > 1 ? 4 / (QPB * DPB) : 1;
     constexpr int SK = SK0 < S4 ? SK0 : S4;
 
-    __shared__ __align__(16) uint4 btile[2][BN * GR];
+    // Three database tiles in flight (loads run two steps ahead) when LDS
+    // allows, else two.
+    constexpr int NBUF = (3 * BN * GR * 16 + 2 * BN * LDQ * 4 <= 144 * 1024) ? 3 : 2;
+    constexpr int LPW = NI / kProducers;  // tile loads per producer wave
+    static_assert(NI % kProducers == 0, "tile loads split evenly over the producers");
+
+    __shared__ __align__(16) uint4 btile[NBUF][BN * GR];
     __shared__ __align__(16) float scores[2][BN * LDQ];
 
     const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)args.nqb * args.nchunks);
@@ -301,23 +321,36 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
     const unsigned char* xb = static_cast<const unsigned char*>(args.xb);
 
     // Load the tile of rows [t0, t0 + BN) into btile[buf]; producers share
-    // the NI granule loads.  Rows past the chunk repeat its last row and
+    // the NI granule loads, LPW per wave, whose per-lane byte offsets inside a
+    // tile are fixed (loff).  Rows past the chunk repeat its last row and
     // granules past the valid elements repeat granule 0: both only ever meet
     // zero A components or unconsumed score columns.
+    int32_t loff[LPW], lrow[LPW], lcc[LPW];
+#pragma unroll
+    for (int t = 0; t < LPW; ++t) {
+        const int g = (wave + t * kProducers) * 64 + lane;
+        const int j = g / GR;
+        const int c = (g % GR) ^ (j & SW);
+        const int cc = c * Op::EPG < args.valid ? c : 0;
+        lrow[t] = j;
+        lcc[t] = cc;
+        loff[t] = (int32_t)(j * row_bytes + cc * 16);
+    }
     auto load_tile = [&](int64_t t0, int buf) {
-        for (int i = wave; i < NI; i += kProducers) {
-            const int g = i * 64 + lane;
-            const int j = g / GR;
-            const int c = (g % GR) ^ (j & SW);
-            int64_t row = t0 + j;
-            row = row < c1 ? row : c1 - 1;
-            const int cc = c * Op::EPG < args.valid ? c : 0;
-            const unsigned char* src = xb + row * row_bytes + (int64_t)cc * 16;
-            uint4* dst = &btile[buf][i * 64];
+        const bool tail = t0 + BN > c1;  // wave-uniform
+#pragma unroll
+        for (int t = 0; t < LPW; ++t) {
+            int64_t row = t0 + lrow[t];
+            const unsigned char* src = xb + t0 * row_bytes + loff[t];
+            if (tail) {
+                row = row < c1 ? row : c1 - 1;
+                src = xb + row * row_bytes + lcc[t] * 16;
+            }
+            uint4* dst = &btile[buf][(wave + t * kProducers) * 64];
             if constexpr (VEC) {
                 __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)dst, 16, 0, 0);
             } else {
-                dst[lane] = load_granule<Op, false>(xb + row * row_bytes, cc, args.valid, true);
+                dst[lane] = load_granule<Op, false>(xb + row * row_bytes, lcc[t], args.valid, true);
             }
         }
     };
@@ -337,12 +370,18 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
             for (int s4 = 0; s4 < S4; ++s4) areg[qb][s4] = load_granule<Op, VEC>(row, 4 * s4 + lh, args.valid, ok);
         }
         if (nsteps > 0) load_tile(c0, 0);
-        __builtin_amdgcn_s_waitcnt(0);
+        if (NBUF == 3 && nsteps > 1) {
+            load_tile(c0 + BN, 1);
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW>());  // tile 0 has landed
+        } else {
+            __builtin_amdgcn_s_waitcnt(0);
+        }
         __syncthreads();
         for (int64_t s = 0; s <= nsteps; ++s) {
             if (s < nsteps) {
-                if (s + 1 < nsteps) load_tile(c0 + (s + 1) * BN, (int)((s + 1) & 1));
-                const uint4* bt = btile[s & 1];
+                const int64_t ahead = s + NBUF - 1;
+                if (ahead < nsteps) load_tile(c0 + ahead * BN, (int)(ahead % NBUF));
+                const uint4* bt = btile[s % NBUF];
                 // All B granules of the step first, so that LDS latency
                 // overlaps the matrix work of earlier granules.
                 uint4 b[S4][DPB];
@@ -382,7 +421,13 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
                         const int j = (dg * DPB + db) * 16 + li;
                         *reinterpret_cast<floatx4*>(&slot[j * LDQ + (qg * QPB + qb) * 16 + 4 * lh]) = v;
                     }
-                __builtin_amdgcn_s_waitcnt(0);
+                // next step's tile (and this step's score stores) must have
+                // landed; with three buffers the loads of the tile after it
+                // may stay in flight
+                if (NBUF == 3 && ahead < nsteps)
+                    __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW>());
+                else
+                    __builtin_amdgcn_s_waitcnt(0);
             }
             __syncthreads();
         }

@@ -26,6 +26,7 @@ struct mk_ivfpq {
     int64_t capacity = 0;
     uint8_t* codes = nullptr;       // [capacity, M], grouped by list
     int64_t* ids = nullptr;         // [capacity]
+    float* t1e = nullptr;           // [capacity] term 1 of Eq. 11 per entry
     int64_t* offsets_dev = nullptr; // [nlist + 1]
     std::vector<int64_t> offsets;   // host copy
 };
@@ -422,6 +423,15 @@ __global__ void probe_labels_kernel(const int64_t* __restrict__ ci, int32_t ld, 
     if (label) label[q] = r;
 }
 
+__global__ void zero_first_kernel(int64_t* __restrict__ a) { a[0] = 0; }
+
+// Workgroups of the list scan per query: ceil(tau / G).
+__global__ void group_count_kernel(const int32_t* __restrict__ tau, int64_t nq, int32_t G,
+                                   int64_t* __restrict__ count) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nq) count[q] = (tau[q] + G - 1) / G;
+}
+
 // tau = clamp(ceil(2^(yhat + delta)), 1, cap) per query; count[q] = tau.
 __global__ void probe_count_kernel(const float* __restrict__ yhat, int64_t nq, float delta,
                                    int32_t cap, int32_t* __restrict__ tau,
@@ -435,25 +445,48 @@ __global__ void probe_count_kernel(const float* __restrict__ yhat, int64_t nq, f
     count[q] = v;
 }
 
+// Term 1 of Eq. 11 per list entry: the query-independent part of its ADC
+// distance, sum over sub-quantizers m of term1[L][m][code_m] (m in order).
+__global__ void entry_term1_kernel(const int64_t* __restrict__ offsets, int32_t M,
+                                   const uint8_t* __restrict__ codes,
+                                   const float* __restrict__ term1, float* __restrict__ t1e) {
+    const int64_t L = blockIdx.x;
+    const float* t1 = term1 + L * (int64_t)M * 256;
+    for (int64_t pos = offsets[L] + threadIdx.x; pos < offsets[L + 1]; pos += blockDim.x) {
+        const uint8_t* c = codes + pos * M;
+        float v = 0.f;
+        for (int m = 0; m < M; ++m) v += t1[m * 256 + c[m]];
+        t1e[pos] = v;
+    }
+}
+
+// One workgroup per (query, group of up to G probed lists).  The query's
+// table -2 term3[q] (Eq. 11) is staged in LDS once for the group; each
+// scanned entry's ADC distance is term 2 (the coarse distance of its list)
+// + its stored term 1 + the M table lookups of its code bytes (Eq. 10-11).
+// Waves take 64 entries at a time, list by list, into WaveSelect queues keyed
+// (distance, list slot << 28 | offset); the 4 queues are merged, and the
+// winners' ids are resolved so that the partial list is keyed (distance, id).
+// Item -> (query, group): fixed probe count nprobe (= ld) when work is null,
+// else query q owns items work[q] .. work[q + 1] - 1 and probes tau[q] lists.
+constexpr int kSlotShift = 28;
+
 template <int KR>
 __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
-    const float* __restrict__ term1, const float* __restrict__ term3,
-    const float* __restrict__ coarse_d, const int64_t* __restrict__ coarse_i,
+    const float* __restrict__ term3, const float* __restrict__ t1e,
+    const float* __restrict__ coarse_d, const int64_t* __restrict__ coarse_i, int32_t ld,
     const int64_t* __restrict__ offsets, const uint8_t* __restrict__ codes,
-    const int64_t* __restrict__ ids, int32_t M, int32_t nprobe, int32_t k,
-    uint64_t* __restrict__ part, const int64_t* __restrict__ work, int64_t nq) {
+    const int64_t* __restrict__ ids, int32_t M, int32_t G, int32_t k,
+    uint64_t* __restrict__ part, const int64_t* __restrict__ work,
+    const int32_t* __restrict__ tau, int64_t nq) {
     constexpr int T = SelParams<KR>::T;
-    constexpr int KS = 64 * KR;
     extern __shared__ __align__(16) unsigned char smem[];
     float* lut = reinterpret_cast<float*>(smem);
     uint64_t* qbuf = reinterpret_cast<uint64_t*>(smem + (size_t)M * 256 * sizeof(float));
 
-    // Work item -> (query, probe rank).  Without a work list every query
-    // probes nprobe lists; with one, query q owns items work[q] ..
-    // work[q + 1] - 1 (its own probe count); the coarse results have nprobe
-    // entries per query either way.
     const int64_t item = blockIdx.x;
-    int64_t q, p;
+    int64_t q, g;
+    int32_t np;
     if (work) {
         int64_t lo = 0, hi = nq;  // largest q with work[q] <= item
         while (hi - lo > 1) {
@@ -461,63 +494,71 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
             if (work[mid] <= item) lo = mid; else hi = mid;
         }
         q = lo;
-        p = item - work[q];
+        g = item - work[q];
+        np = tau[q];
     } else {
-        q = item / nprobe;
-        p = item - q * nprobe;
+        const int64_t ng = (ld + G - 1) / G;
+        q = item / ng;
+        g = item - q * ng;
+        np = ld;
     }
+    const int32_t p0 = (int32_t)(g * G);
+    const int32_t ns = np - p0 < G ? np - p0 : G;  // lists in this group
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int64_t L = coarse_i[q * nprobe + p];
-    const float term2 = coarse_d[q * nprobe + p];
     uint64_t* out = part + item * k;
 
-    if (L < 0) {  // fewer lists than probes: nothing to scan (wave-uniform)
-        for (int e = threadIdx.x; e < k; e += 64 * kScanWaves) out[e] = kSentinel;
-        return;
-    }
-    const float* t1 = term1 + L * (int64_t)M * 256;
     const float* t3 = term3 + q * (int64_t)M * 256;
-    for (int e = threadIdx.x; e < M * 256; e += 64 * kScanWaves) lut[e] = fmaf(-2.f, t3[e], t1[e]);
+    for (int e = threadIdx.x; e < M * 256; e += 64 * kScanWaves) lut[e] = -2.f * t3[e];
     __syncthreads();
-
-    const int64_t lo = offsets[L];
-    const int64_t n = offsets[L + 1] - lo;
-    const uint8_t* lc = codes + lo * M;
 
     WaveSelect<KR, T> ws;
     ws.init(k);
     const bool vec16 = (M & 15) == 0;
+    const int64_t* cirow = coarse_i + q * ld + p0;
+    const float* cdrow = coarse_d + q * ld + p0;
 #pragma unroll 1
-    for (int64_t e0 = (int64_t)wave * 64; e0 < n; e0 += 64 * kScanWaves) {
-        const int64_t e = e0 + lane;
-        float dist = term2;
-        const bool ok = e < n;
-        if (ok) {
-            const uint8_t* c = lc + e * M;
-            if (vec16) {
-                for (int m0 = 0; m0 < M; m0 += 16) {
-                    const uint4 w = *reinterpret_cast<const uint4*>(c + m0);
-                    const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+    for (int32_t sl = 0; sl < ns; ++sl) {
+        const int64_t L = cirow[sl];
+        if (L < 0) continue;  // fewer lists than probes (wave-uniform)
+        const float term2 = cdrow[sl];
+        const int64_t lo = offsets[L];
+        const int64_t n = offsets[L + 1] - lo;
+        const uint8_t* lc = codes + lo * M;
+        const float* lt = t1e + lo;
+#pragma unroll 1
+        for (int64_t e0 = (int64_t)wave * 64; e0 < n; e0 += 64 * kScanWaves) {
+            const int64_t e = e0 + lane;
+            const bool ok = e < n;
+            float dist = 0.f;
+            if (ok) {
+                dist = term2 + lt[e];
+                const uint8_t* c = lc + e * M;
+                if (vec16) {
+                    for (int m0 = 0; m0 < M; m0 += 16) {
+                        const uint4 w = *reinterpret_cast<const uint4*>(c + m0);
+                        const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-                    for (int h = 0; h < 4; ++h) {
+                        for (int h = 0; h < 4; ++h) {
 #pragma unroll
-                        for (int b = 0; b < 4; ++b) {
-                            const int m = m0 + 4 * h + b;
-                            dist += lut[m * 256 + ((ww[h] >> (8 * b)) & 0xFF)];
+                            for (int b = 0; b < 4; ++b) {
+                                const int m = m0 + 4 * h + b;
+                                dist += lut[m * 256 + ((ww[h] >> (8 * b)) & 0xFF)];
+                            }
                         }
                     }
-                }
-            } else {
-                for (int m0 = 0; m0 < M; m0 += 4) {
-                    const uint32_t w = *reinterpret_cast<const uint32_t*>(c + m0);
+                } else {
+                    for (int m0 = 0; m0 < M; m0 += 4) {
+                        const uint32_t w = *reinterpret_cast<const uint32_t*>(c + m0);
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) dist += lut[(m0 + b) * 256 + ((w >> (8 * b)) & 0xFF)];
+                        for (int b = 0; b < 4; ++b) dist += lut[(m0 + b) * 256 + ((w >> (8 * b)) & 0xFF)];
+                    }
                 }
             }
+            const uint64_t key =
+                ok ? make_key(dist, ((uint32_t)sl << kSlotShift) | (uint32_t)e) : kSentinel;
+            if (ws.push(key)) ws.merge();
         }
-        const uint64_t key = ok ? make_key(dist, (uint32_t)e) : kSentinel;
-        if (ws.push(key)) ws.merge();
     }
     ws.finish();
 
@@ -543,33 +584,49 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
             const int e = r * 64 + lane;
             if (e < k) {
                 const uint64_t key = fin.w[r];
-                out[e] = key == kSentinel
-                             ? kSentinel
-                             : ((key & 0xFFFFFFFF00000000ull) | (uint32_t)ids[lo + key_index(key)]);
+                uint64_t o = kSentinel;
+                if (key != kSentinel) {
+                    const uint32_t v = key_index(key);
+                    const int64_t L = cirow[v >> kSlotShift];
+                    const int64_t id = ids[offsets[L] + (v & ((1u << kSlotShift) - 1))];
+                    o = (key & 0xFFFFFFFF00000000ull) | (uint32_t)id;
+                }
+                out[e] = o;
             }
         }
     }
 }
 
-mk_status launch_scan(const float* term1, const float* term3, const float* cd, const int64_t* ci,
-                      const int64_t* offsets, const uint8_t* codes, const int64_t* ids, int32_t M,
-                      int64_t nq, int32_t nprobe, int32_t k, uint64_t* part, hipStream_t s,
-                      const int64_t* work = nullptr, int64_t nwork = 0) {
-    const int64_t items = work ? nwork : nq * nprobe;
+// Lists per workgroup: enough workgroups for the chip (about 8 per CU)
+// while sharing each query's table over as many lists as possible.
+int32_t scan_group(int64_t total_probes) {
+    const int64_t g = total_probes / 2048;
+    return (int32_t)(g < 1 ? 1 : g > 16 ? 16 : g);
+}
+
+mk_status launch_scan(const float* term3, const float* t1e, const float* cd, const int64_t* ci,
+                      int32_t ld, const int64_t* offsets, const uint8_t* codes,
+                      const int64_t* ids, int32_t M, int64_t nq, int32_t G, int32_t k,
+                      uint64_t* part, int64_t items, hipStream_t s,
+                      const int64_t* work = nullptr, const int32_t* tau = nullptr) {
     if (items == 0) return MK_OK;
-    MK_REQUIRE(items < (1ll << 31), MK_ERR_UNSUPPORTED, "nq * nprobe too large for one launch");
+    MK_REQUIRE(items < (1ll << 31), MK_ERR_UNSUPPORTED, "too many scan items for one launch");
     const size_t shm = (size_t)M * 256 * sizeof(float) + (size_t)kScanWaves * k * sizeof(uint64_t);
     MK_REQUIRE(shm <= 65536, MK_ERR_UNSUPPORTED,
                "lookup tables plus merge buffers exceed 64 KiB of LDS (reduce M or k)");
     const dim3 grid((unsigned)items), block(64 * kScanWaves);
     ProfScope prof("ivf_scan", s);
+#define MK_SCAN(KR)                                                                          \
+    hipLaunchKernelGGL(ivf_scan<KR>, grid, block, shm, s, term3, t1e, cd, ci, ld, offsets,  \
+                       codes, ids, M, G, k, part, work, tau, nq)
     switch (queue_regs(k)) {
-        case 1: hipLaunchKernelGGL(ivf_scan<1>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part, work, nq); break;
-        case 2: hipLaunchKernelGGL(ivf_scan<2>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part, work, nq); break;
-        case 4: hipLaunchKernelGGL(ivf_scan<4>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part, work, nq); break;
-        case 8: hipLaunchKernelGGL(ivf_scan<8>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part, work, nq); break;
-        default: hipLaunchKernelGGL(ivf_scan<16>, grid, block, shm, s, term1, term3, cd, ci, offsets, codes, ids, M, nprobe, k, part, work, nq); break;
+        case 1: MK_SCAN(1); break;
+        case 2: MK_SCAN(2); break;
+        case 4: MK_SCAN(4); break;
+        case 8: MK_SCAN(8); break;
+        default: MK_SCAN(16); break;
     }
+#undef MK_SCAN
     MK_LAUNCHED();
     return MK_OK;
 }
@@ -588,6 +645,7 @@ mk_status build_term1(mk_ivfpq* ix, hipStream_t s) {
 void reset_lists(mk_ivfpq* ix) {
     free_dev(reinterpret_cast<void*&>(ix->codes));
     free_dev(reinterpret_cast<void*&>(ix->ids));
+    free_dev(reinterpret_cast<void*&>(ix->t1e));
     ix->ntotal = 0;
     ix->capacity = 0;
     ix->offsets.assign(ix->nlist + 1, 0);
@@ -695,6 +753,10 @@ mk_status add(mk_ivfpq* ix, const float* xb, int64_t nb, hipStream_t s) {
         no[L + 1] = no[L] + (ix->offsets[L + 1] - ix->offsets[L]) + (int64_t)hc[L];
     }
     const int64_t total = no[nlist];
+    MK_REQUIRE(total < (1ll << 32) - 1, MK_ERR_UNSUPPORTED, "an index holds fewer than 2^32 - 1 vectors");
+    for (int32_t L = 0; L < nlist; ++L)
+        MK_REQUIRE(no[L + 1] - no[L] < (1ll << kSlotShift), MK_ERR_UNSUPPORTED,
+                   "an inverted list holds fewer than 2^28 entries");
     uint8_t* ncodes = nullptr;
     int64_t* nids = nullptr;
     MK_TRY(alloc_dev(ncodes, (size_t)total * M));
@@ -726,53 +788,60 @@ mk_status add(mk_ivfpq* ix, const float* xb, int64_t nb, hipStream_t s) {
     ix->capacity = total;
     ix->ntotal = total;
     ix->offsets = no;
-    return upload_offsets(ix, s);
+    MK_TRY(upload_offsets(ix, s));
+    // per-entry term 1 of Eq. 11 for the new list layout
+    free_dev(reinterpret_cast<void*&>(ix->t1e));
+    MK_TRY(alloc_dev(ix->t1e, (size_t)total));
+    hipLaunchKernelGGL(entry_term1_kernel, dim3(nlist), dim3(kBlock), 0, s, ix->offsets_dev, M,
+                       ix->codes, ix->term1, ix->t1e);
+    MK_LAUNCHED();
+    MK_HIP(hipStreamSynchronize(s));
+    return MK_OK;
+}
+
+// Steps shared by the fixed-probe searches: the probe set and term 2 by exact
+// search over the coarse centroids (Eq. 5), term 3 per query, and the list
+// scan into `part` = per query `ngroups` partial lists of kk keys.
+mk_status scan_fixed(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t nprobe, int32_t kk,
+                     Scratch& part, int64_t* ngroups, hipStream_t s) {
+    const int32_t M = ix->M;
+    Scratch cd, ci, t3;
+    MK_TRY(cd.alloc(sizeof(float) * nq * nprobe, s));
+    MK_TRY(ci.alloc(sizeof(int64_t) * nq * nprobe, s));
+    MK_TRY(t3.alloc(sizeof(float) * nq * M * 256, s));
+    const int32_t G = scan_group(nq * nprobe);
+    *ngroups = ceil_div(nprobe, G);
+    MK_TRY(part.alloc(sizeof(uint64_t) * nq * *ngroups * kk, s));
+    MK_TRY(knn_search(xq, nq, ix->coarse, ix->coarse_norms, ix->nlist, ix->d, nprobe,
+                      MK_METRIC_L2, cd.as<float>(), ci.as<int64_t>(), s));
+    hipLaunchKernelGGL(term3_kernel, dim3(grid_of(nq * M * 256)), dim3(kBlock), 0, s, xq, nq, M,
+                       ix->dsub, ix->books, t3.as<float>());
+    MK_LAUNCHED();
+    return launch_scan(t3.as<float>(), ix->t1e, cd.as<float>(), ci.as<int64_t>(), nprobe,
+                       ix->offsets_dev, ix->codes, ix->ids, M, nq, G, kk, part.as<uint64_t>(),
+                       nq * *ngroups, s);
 }
 
 mk_status search(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t k, int32_t nprobe, float* D,
                  int64_t* I, hipStream_t s) {
-    const int32_t M = ix->M;
-    Scratch cd, ci, t3, part;
-    MK_TRY(cd.alloc(sizeof(float) * nq * nprobe, s));
-    MK_TRY(ci.alloc(sizeof(int64_t) * nq * nprobe, s));
-    MK_TRY(t3.alloc(sizeof(float) * nq * M * 256, s));
-    MK_TRY(part.alloc(sizeof(uint64_t) * nq * nprobe * k, s));
-    // Eq. 5: probe set and term 2 by exact search over the coarse centroids
-    MK_TRY(knn_search(xq, nq, ix->coarse, ix->coarse_norms, ix->nlist, ix->d, nprobe,
-                      MK_METRIC_L2, cd.as<float>(), ci.as<int64_t>(), s));
-    // term 3 per query
-    hipLaunchKernelGGL(term3_kernel, dim3(grid_of(nq * M * 256)), dim3(kBlock), 0, s, xq, nq, M,
-                       ix->dsub, ix->books, t3.as<float>());
-    MK_LAUNCHED();
-    MK_TRY(launch_scan(ix->term1, t3.as<float>(), cd.as<float>(), ci.as<int64_t>(),
-                       ix->offsets_dev, ix->codes, ix->ids, M, nq, nprobe, k,
-                       part.as<uint64_t>(), s));
+    Scratch part;
+    int64_t ng = 0;
+    MK_TRY(scan_fixed(ix, xq, nq, nprobe, k, part, &ng, s));
     ProfScope prof("ivf_merge", s);
-    return merge_key_lists(part.as<uint64_t>(), nq, nprobe, k, D, I, s);
+    return merge_key_lists(part.as<uint64_t>(), nq, (int32_t)ng, k, D, I, s);
 }
 
 // IVFADC short list of R entries per query, then exact re-ranking of that
 // list against the full-precision database rows (row id of xb = vector id).
 mk_status search_rerank(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t k, int32_t nprobe,
                         int32_t R, const float* xb, float* D, int64_t* I, hipStream_t s) {
-    const int32_t M = ix->M;
-    Scratch cd, ci, t3, part, keys;
-    MK_TRY(cd.alloc(sizeof(float) * nq * nprobe, s));
-    MK_TRY(ci.alloc(sizeof(int64_t) * nq * nprobe, s));
-    MK_TRY(t3.alloc(sizeof(float) * nq * M * 256, s));
-    MK_TRY(part.alloc(sizeof(uint64_t) * nq * nprobe * R, s));
+    Scratch part, keys;
+    int64_t ng = 0;
+    MK_TRY(scan_fixed(ix, xq, nq, nprobe, R, part, &ng, s));
     MK_TRY(keys.alloc(sizeof(uint64_t) * nq * 64 * queue_regs(R), s));
-    MK_TRY(knn_search(xq, nq, ix->coarse, ix->coarse_norms, ix->nlist, ix->d, nprobe,
-                      MK_METRIC_L2, cd.as<float>(), ci.as<int64_t>(), s));
-    hipLaunchKernelGGL(term3_kernel, dim3(grid_of(nq * M * 256)), dim3(kBlock), 0, s, xq, nq, M,
-                       ix->dsub, ix->books, t3.as<float>());
-    MK_LAUNCHED();
-    MK_TRY(launch_scan(ix->term1, t3.as<float>(), cd.as<float>(), ci.as<int64_t>(),
-                       ix->offsets_dev, ix->codes, ix->ids, M, nq, nprobe, R,
-                       part.as<uint64_t>(), s));
     {
         ProfScope prof("ivf_merge", s);
-        MK_TRY(merge_key_lists(part.as<uint64_t>(), nq, nprobe, R, nullptr, nullptr, s,
+        MK_TRY(merge_key_lists(part.as<uint64_t>(), nq, (int32_t)ng, R, nullptr, nullptr, s,
                                keys.as<uint64_t>()));
     }
     return rerank_keys(keys.as<uint64_t>(), nq, R, xq, xb, ix->d, true, k, D, I, s);
@@ -840,26 +909,38 @@ mk_status search_learned(mk_ivfpq* ix, const mk_mlp* net, float delta, const flo
     MK_LAUNCHED();
     if (used)
         MK_HIP(hipMemcpyAsync(used, tau.ptr, sizeof(int32_t) * nq, hipMemcpyDeviceToDevice, s));
-    // work[0] = 0, work[q + 1] = tau[0] + ... + tau[q]
-    MK_HIP(hipMemsetAsync(work.ptr, 0, sizeof(int64_t), s));
+    // exclusive prefix sums of per-query counts: work[0] = 0, work[q + 1] =
+    // cnt[0] + ... + cnt[q]; returns the total (synchronises)
     size_t tmp_bytes = 0;
     MK_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, cnt.as<int64_t>(),
                                             work.as<int64_t>() + 1, (int)nq, s));
     MK_TRY(tmp.alloc(tmp_bytes, s));
-    MK_HIP(hipcub::DeviceScan::InclusiveSum(tmp.ptr, tmp_bytes, cnt.as<int64_t>(),
-                                            work.as<int64_t>() + 1, (int)nq, s));
-    int64_t nwork = 0;
-    MK_HIP(hipMemcpyAsync(&nwork, work.as<int64_t>() + nq, sizeof(int64_t),
-                          hipMemcpyDeviceToHost, s));
-    MK_HIP(hipStreamSynchronize(s));
+    auto prefix = [&](int64_t* total) -> mk_status {
+        hipLaunchKernelGGL(zero_first_kernel, dim3(1), dim3(1), 0, s, work.as<int64_t>());
+        MK_LAUNCHED();
+        MK_HIP(hipcub::DeviceScan::InclusiveSum(tmp.ptr, tmp_bytes, cnt.as<int64_t>(),
+                                                work.as<int64_t>() + 1, (int)nq, s));
+        MK_HIP(hipMemcpyAsync(total, work.as<int64_t>() + nq, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, s));
+        MK_HIP(hipStreamSynchronize(s));
+        return MK_OK;
+    };
+    int64_t probes = 0, nwork = 0;
+    MK_TRY(prefix(&probes));
+    // lists per workgroup from the total probe count, then workgroups per query
+    const int32_t G = scan_group(probes);
+    hipLaunchKernelGGL(group_count_kernel, dim3(grid_of(nq)), dim3(kBlock), 0, s,
+                       tau.as<int32_t>(), nq, G, cnt.as<int64_t>());
+    MK_LAUNCHED();
+    MK_TRY(prefix(&nwork));
     MK_TRY(t3.alloc(sizeof(float) * nq * M * 256, s));
     MK_TRY(part.alloc(sizeof(uint64_t) * nwork * kk, s));
     hipLaunchKernelGGL(term3_kernel, dim3(grid_of(nq * M * 256)), dim3(kBlock), 0, s, xq, nq, M,
                        ix->dsub, ix->books, t3.as<float>());
     MK_LAUNCHED();
-    MK_TRY(launch_scan(ix->term1, t3.as<float>(), cd.as<float>(), ci.as<int64_t>(),
-                       ix->offsets_dev, ix->codes, ix->ids, M, nq, cap, kk, part.as<uint64_t>(),
-                       s, work.as<int64_t>(), nwork));
+    MK_TRY(launch_scan(t3.as<float>(), ix->t1e, cd.as<float>(), ci.as<int64_t>(), cap,
+                       ix->offsets_dev, ix->codes, ix->ids, M, nq, G, kk, part.as<uint64_t>(),
+                       nwork, s, work.as<int64_t>(), tau.as<int32_t>()));
     if (R <= 0) {
         ProfScope prof("ivf_merge", s);
         return merge_key_lists(part.as<uint64_t>(), nq, 0, k, D, I, s, nullptr,
@@ -930,6 +1011,7 @@ extern "C" void mk_ivfpq_destroy(mk_ivfpq* ix) {
     mk::free_dev(reinterpret_cast<void*&>(ix->term1));
     mk::free_dev(reinterpret_cast<void*&>(ix->codes));
     mk::free_dev(reinterpret_cast<void*&>(ix->ids));
+    mk::free_dev(reinterpret_cast<void*&>(ix->t1e));
     mk::free_dev(reinterpret_cast<void*&>(ix->offsets_dev));
     delete ix;
 }

@@ -189,18 +189,31 @@ __device__ __forceinline__ uint64_t ws_element(const uint64_t (&w)[KR], int pos)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Append `key` to this lane's thread queue when `take` (slot order does not
-// matter: the merge sorts the whole array).
+// The thread queues of a wave form one buffer of 64*T keys in lane-stride
+// order (position p in register p / 64 of lane p % 64) that is filled densely:
+// the keys of the lanes whose `take` is set (`bal` = their ballot) go to
+// positions count, count + 1, ... in lane order, moved there by one forward
+// permute (lanes without a key are sent to the remaining lanes, so the
+// permute is a bijection).  Order inside the buffer does not matter, the merge
+// sorts it.  Returns the new count; count + popcount(bal) <= 64*T.
 template <int T>
-__device__ __forceinline__ void tq_push(uint64_t (&tq)[T], uint64_t key, bool take) {
+__device__ __forceinline__ int tq_append(uint64_t (&tq)[T], uint64_t key, bool take,
+                                         uint64_t bal, int count) {
+    const int lane = lane_id();
+    const int n = __popcll(bal);
+    const int below = (int)__builtin_amdgcn_mbcnt_hi(
+        (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    const int base = count & 63;
+    const int dst = take ? (base + below) & 63 : (base + n + (lane - below)) & 63;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)(uint32_t)key);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)(uint32_t)(key >> 32));
+    const uint64_t got = ((uint64_t)hi << 32) | lo;
+    const int rel = (lane - base) & 63;  // this lane holds position count + rel
+    const bool valid = rel < n;
+    const int reg = (count + rel) >> 6;
 #pragma unroll
-    for (int i = T - 1; i > 0; --i) tq[i] = take ? tq[i - 1] : tq[i];
-    tq[0] = take ? key : tq[0];
-}
-
-template <int T>
-__device__ __forceinline__ bool tq_full(const uint64_t (&tq)[T]) {
-    return tq[T - 1] != kSentinel;
+    for (int i = 0; i < T; ++i) tq[i] = (valid && reg == i) ? got : tq[i];
+    return count + n;
 }
 
 // Single-stream selector: one wave selects the `keff` smallest keys of a
@@ -215,6 +228,7 @@ struct WaveSelect {
     uint64_t kth;   // current keff-th smallest key (sentinel until W holds keff)
     float kth_f;    // its score; +inf while kth is the sentinel
     int keff;
+    int cnt;        // keys in the thread-queue buffer (wave-uniform)
 
     __device__ __forceinline__ void init(int k_eff) {
 #pragma unroll
@@ -224,20 +238,24 @@ struct WaveSelect {
         kth = kSentinel;
         kth_f = INFINITY;
         keff = k_eff;
+        cnt = 0;
     }
 
     __device__ __forceinline__ void merge() {
         ws_merge<KR, T>(w, tq);
+        cnt = 0;
         kth = ws_element<KR>(w, keff - 1);
         kth_f = kth == kSentinel ? INFINITY : key_score(kth);
     }
 
-    // Offer one key per lane; returns true (wave-uniform) when a merge is due.
+    // Offer one key per lane; returns true (wave-uniform) when a merge is due
+    // (the buffer might not hold another 64 keys).
     __device__ __forceinline__ bool push(uint64_t key) {
         const bool take = key < kth;
-        if (__any(take)) {
-            tq_push<T>(tq, key, take);
-            return __any(tq_full<T>(tq));
+        const uint64_t bal = __ballot(take);
+        if (bal) {
+            cnt = tq_append<T>(tq, key, take, bal, cnt);
+            return cnt > 64 * (T - 1);
         }
         return false;
     }

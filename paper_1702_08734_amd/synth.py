@@ -140,9 +140,18 @@ def ivfpq_workload(nb: int = 10_000_000, nq: int = 10_000, nt: int = 500_000):
             "coarse_init": choose_rows(nt, 4096, (103, 3)),
             "pq_init": pq_init_rows(nt, 16, (103, 4)), "k": 100,
             "nprobes": (1, 8, 16, 32, 64, 128), "rerank": (256, 1024),
-            "learn_rerank": 256, "learn_cap": 256, "learn_fixed_nprobes": tuple(range(1, 13)),
+            "learn_rerank": 256, "learn_cap": 32, "learn_fixed_nprobes": tuple(range(1, 13)),
             "learn_train": 200_000, "learn_epochs": 10, "serve_requests": 2000,
             "serve_load": (0.5, 0.8)}
+
+
+def lowp_workload(nb: int = 20_000_000, nq: int = 10_000):
+    """Low-precision brute-force workload: unit-norm rows of a 2,000-component
+    mixture in d = 96 (database and queries), k = 100, re-rank depth 4k."""
+    mix = Mixture(2000, 96, (104, 99))
+    return {"xb": mix.sample(nb, (104, 0), unit_norm=True),
+            "xq": mix.sample(nq, (104, 1), unit_norm=True), "k": 100, "R": 400,
+            "metrics": ("ip", "l2")}
 
 
 def mlp_init(din: int, hidden: int, seed) -> np.ndarray:
