@@ -267,25 +267,26 @@ def learned_probe_section(api, synth, torch, ix, xb, xq, w, recalls):
         fixed.append({"nprobe": nprobe, "ms": round(dt * 1e3, 3), "qps": round(nq / dt, 1),
                       "recall_at_10": r1, "ten_intersection": r2})
     progress("learned probe: labels for training queries")
-    mix = synth.Mixture(1000, 128, (103, 99))
-    xtr = torch.from_numpy(mix.sample(w["learn_train"], (103, 20))).cuda()
+    base = w["base"]
+    mix = synth.Mixture(*w["mix"])
+    xtr = torch.from_numpy(mix.sample(w["learn_train"], (base, 20))).cuda()
     nn = torch.cat([api.knn_search(xtr[i:i + 20000], xb, 1)[1][:, 0]
                     for i in range(0, xtr.shape[0], 20000)]).contiguous()
     F = ix.probe_features(xtr)
     target, label = ix.probe_labels(xtr, nn, cap)
     net = api.MLP(128 + 32, 256, "bf16")
-    net.set_params(synth.mlp_init(160, 256, (103, 21)))
+    net.set_params(synth.mlp_init(160, 256, (base, 21)))
     net.fit_standardization(F)
     progress("learned probe: training")
     t0 = time.perf_counter()
     losses = []
     for ep in range(w["learn_epochs"]):
-        perm = torch.from_numpy(synth.permutation(F.shape[0], (103, 22, ep))).cuda()
+        perm = torch.from_numpy(synth.permutation(F.shape[0], (base, 22, ep))).cuda()
         losses.append(float(net.train_epoch(F, target, perm, 1024, 1e-3).mean().item()))
     t_train = time.perf_counter() - t0
     # calibrate the offset on held-out queries: smallest delta reaching 0.9
     progress("learned probe: calibration")
-    xcal = torch.from_numpy(mix.sample(10_000, (103, 23))).cuda()
+    xcal = torch.from_numpy(mix.sample(10_000, (base, 23))).cuda()
     gcal = api.knn_search(xcal, xb, 1)[1][:, 0].cpu().numpy()
     delta = None
     for dlt in np.arange(-1.0, 4.01, 0.25):
@@ -328,7 +329,7 @@ def serving_section(api, synth, torch, ix, xb, xq, w, learned):
         mode = f"fixed probe count {cfg['nprobe']}"
     xq_h = xq.cpu().numpy()
     nreq = w["serve_requests"]
-    rng = np.random.default_rng(np.random.SeedSequence((103, 24)))
+    rng = np.random.default_rng(np.random.SeedSequence((w["base"], 24)))
     sizes = np.clip(np.floor(np.exp(rng.random(nreq) * np.log(1025))), 1, 1024).astype(int)
     starts = rng.integers(0, xq_h.shape[0] - 1024, nreq)
     gaps = rng.exponential(1.0, nreq)
@@ -379,6 +380,48 @@ def serving_section(api, synth, torch, ix, xb, xq, w, learned):
     return res
 
 
+def ivf_large_run(api, synth, torch):
+    """IVFADC at 50,000,000 x 128 (16,384 lists, PQ 16): fixed vs learned probe
+    count at R@10 >= 0.9 with the same exact re-rank depth, and serving
+    latencies; one JSON record."""
+    import numpy as np
+    progress("ivf-large: generating 50,000,000 x 128 mixture")
+    w = synth.ivfpq_large_workload()
+    xb = torch.from_numpy(w["xb"]).cuda()
+    del w["xb"]
+    xq = torch.from_numpy(w["xq"]).cuda()
+    xt = xb[torch.from_numpy(w["sample"]).cuda()].contiguous()
+    ix = api.IVFPQ(128, w["nlist"], w["M"])
+    progress("ivf-large: training")
+    t0 = time.perf_counter()
+    ix.train(xt, 20, w["coarse_init"], w["pq_init"])
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del xt
+    progress("ivf-large: adding")
+    t0 = time.perf_counter()
+    ix.add(xb)
+    torch.cuda.synchronize()
+    t_add = time.perf_counter() - t0
+    progress("ivf-large: ground truth")
+    gt = api.knn_search(xq, xb, 10)[1].cpu().numpy()
+    nq = xq.shape[0]
+
+    def recalls(I):
+        I = I.cpu().numpy()[:, :10]
+        r1 = float(np.mean([gt[j, 0] in I[j] for j in range(nq)]))
+        r2 = float(np.mean([len(set(gt[j]) & set(I[j])) / 10 for j in range(nq)]))
+        return round(r1, 4), round(r2, 4)
+
+    learned = learned_probe_section(api, synth, torch, ix, xb, xq, w, recalls)
+    serving = serving_section(api, synth, torch, ix, xb, xq, w, learned)
+    return {"metric": "IVFADC queries/s at R@10 >= 0.9 (learned vs fixed probe count, exact re-rank)",
+            "workload": "50,000,000 x 128 1,000-component mixture, nlist 16384, PQ 16 x 8 bit, "
+                        "10,000 queries, k = 10, re-rank R = 256",
+            "train_s": round(t_train, 2), "add_s": round(t_add, 2),
+            "learned_probe": learned, "serving": serving}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -390,6 +433,8 @@ def main() -> int:
                     help="only the exact-search measurement (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device (HBM byte-counter calibration)")
+    ap.add_argument("--ivf-large", action="store_true",
+                    help="only the 50,000,000-vector IVFADC learned-probe and serving run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are "
@@ -406,6 +451,10 @@ def main() -> int:
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}))
         return 0
     from paper_1702_08734_amd import api, synth
+
+    if args.ivf_large:
+        print(json.dumps(ivf_large_run(api, synth, torch)), flush=True)
+        return 0
 
     progress("exact: generating 1,000,000 x 128 mixture")
     w = synth.exact_large()

@@ -5,6 +5,8 @@
 // direct-form FP32 re-rank of the kept candidates.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "kselect.hpp"
 #include "profile.hpp"
@@ -126,6 +128,116 @@ struct MultiSelect {
     }
 };
 
+// QW selectors whose wave queues (64*KR keys per query, lane-stride) live in
+// device memory -- the kernel's own partial-result rows -- instead of
+// registers: only the dense thread-queue buffers and the per-query k-th keys
+// stay in registers, so one consumer can serve as many queries for 256- and
+// 1024-entry queues as for short ones.  A merge loads the query's wave
+// queue (each lane its own keys, so a lane only ever reads what it wrote),
+// merges the buffer in, and stores it back.  Queries at or beyond nvalid
+// never take candidates and are never written.
+template <int KR, int T, int QW>
+struct GlobalSelect {
+    static constexpr int kQueries = QW;
+    typedef uint32_t vq __attribute__((ext_vector_type(QW)));
+    typedef float vqf __attribute__((ext_vector_type(QW)));
+    vq tl[T], th[T];     // thread-queue buffers
+    vq kl, kh;           // key of each query's current k-th entry (wave-uniform)
+    vqf kf;              // its score, or the bound below if that is smaller
+    vqf bd;              // score bound from other database chunks
+    int cnt[QW];
+    uint32_t stored;     // bit q: query q's queue in memory holds merged keys
+    uint64_t* wbase;     // queue of query q at wbase + q * wstride
+    int64_t wstride;
+    int keff, nvalid;
+
+    __device__ __forceinline__ void init(int k_eff, uint64_t* base, int64_t stride, int valid) {
+        keff = k_eff;
+        wbase = base;
+        wstride = stride;
+        nvalid = valid;
+#pragma unroll
+        for (int i = 0; i < T; ++i) tl[i] = th[i] = ~0u;
+        kl = kh = ~0u;
+        kf = INFINITY;
+        bd = INFINITY;
+#pragma unroll
+        for (int q = 0; q < QW; ++q) {
+            cnt[q] = 0;
+            if (q >= valid) kf[q] = -INFINITY;
+        }
+        stored = 0;
+    }
+
+    __device__ __forceinline__ void bound(int q, float b) {
+        bd[q] = fminf(bd[q], b);
+        kf[q] = fminf(kf[q], b);
+    }
+
+    __device__ __forceinline__ void merge_slot(int q) {
+        const int lane = lane_id();
+        uint64_t* wp = wbase + (int64_t)q * wstride;
+        const bool have = (stored >> q) & 1u;
+        uint64_t ww[KR], tt[T];
+#pragma unroll
+        for (int r = 0; r < KR; ++r) ww[r] = have ? wp[r * 64 + lane] : kSentinel;
+#pragma unroll
+        for (int i = 0; i < T; ++i) tt[i] = ((uint64_t)th[i][q] << 32) | tl[i][q];
+        ws_merge<KR, T>(ww, tt);
+        const uint64_t kk = ws_element<KR>(ww, keff - 1);
+#pragma unroll
+        for (int r = 0; r < KR; ++r) wp[r * 64 + lane] = ww[r];
+        stored |= 1u << q;
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            tl[i][q] = ~0u;
+            th[i][q] = ~0u;
+        }
+#pragma unroll
+        for (int qq = 0; qq < QW; ++qq) cnt[qq] = qq == q ? 0 : cnt[qq];
+        kl[q] = (uint32_t)kk;
+        kh[q] = (uint32_t)(kk >> 32);
+        kf[q] = fminf(kk == kSentinel ? INFINITY : key_score(kk), bd[q]);
+    }
+
+    __device__ __forceinline__ void offer(const float (&score)[QW], uint32_t idx, bool ok) {
+        uint32_t full = 0;
+#pragma unroll
+        for (int q = 0; q < QW; ++q) {
+            if (__any(ok && score[q] <= kf[q])) {
+                const uint64_t key = ok ? make_key(score[q], idx) : kSentinel;
+                const uint64_t kth = ((uint64_t)kh[q] << 32) | kl[q];
+                const bool take = key < kth;
+                const uint64_t bal = __ballot(take);
+                if (bal) {
+                    uint64_t tq[T];
+#pragma unroll
+                    for (int i = 0; i < T; ++i) tq[i] = ((uint64_t)th[i][q] << 32) | tl[i][q];
+                    cnt[q] = tq_append<T>(tq, key, take, bal, cnt[q]);
+#pragma unroll
+                    for (int i = 0; i < T; ++i) {
+                        tl[i][q] = (uint32_t)tq[i];
+                        th[i][q] = (uint32_t)(tq[i] >> 32);
+                    }
+                    if (cnt[q] > 64 * (T - 1)) full |= 1u << q;
+                }
+            }
+        }
+        while (full) {
+            const int q = __builtin_ctz(full);
+            full &= full - 1;
+            merge_slot(q);
+        }
+    }
+
+    // Final merge of every valid query (also writes the all-sentinel queue
+    // of a query that never took a candidate).
+    __device__ __forceinline__ void finish() {
+#pragma unroll 1
+        for (int q = 0; q < nvalid; ++q) merge_slot(q);
+    }
+};
+
 // ---------------------------------------------------------------- operands
 // Operand formats of the distance tile.  A 16-byte granule holds EPG
 // elements; lane (i, h) of a 16x16 MFMA block supplies granule 4*s + h of
@@ -207,25 +319,23 @@ constexpr int waitcnt_vm() {
 
 // Workgroup of the fused kernel: 4 producer waves (one per SIMD) compute the
 // q.y tile of BQ queries x BN = 64 database rows per step on the matrix
-// cores and write it to one of two LDS slots, while consumer waves run the
+// cores and write it to one of two LDS slots, while 4 consumer waves run the
 // selectors of the previous step's tile from the other slot -- MFMA and VALU
 // selection overlap, one barrier per step.  Each producer owns QPB query
 // blocks x DPB database blocks of 16 (a 4-producer grid of QG x DG), each
-// consumer QW = BQ/NC queries.  Sizes per wave-queue length KR and padded row
-// bytes RB: KR <= 2: BQ 64 (QW 16); KR = 4: BQ 32 (QW 8); KR >= 8 or rows
-// over 512 bytes: BQ 16 (QW 4, or QW 2 over 8 consumer waves for KR = 16).
+// consumer QW = BQ/4 queries.  BQ = 64, or 16 for rows over 512 bytes (LDS).
 constexpr int kProducers = 4;
 
 template <int KR, int RB>
 struct FusedShape {
-    static constexpr int NC = KR >= 16 ? 8 : 4;
-    // thread-queue length: shorter than the stand-alone selector's for 256-
-    // and 1024-entry queues so that a consumer's selectors and working copy
-    // fit its registers
-    static constexpr int T = KR >= 16 ? 4 : KR == 4 ? 2 : SelParams<KR>::T;
+    // queues of 256 entries and more live in device memory (GlobalSelect)
+    static constexpr bool mem_queues = KR >= 4;
+    static constexpr int NC = 4;
+    // thread-queue buffer: 64*T keys per query
+    static constexpr int T = mem_queues ? 2 : SelParams<KR>::T;
     static constexpr bool wide = RB > 512;
-    static constexpr int QPB = (!wide && KR <= 2) ? 2 : 1;
-    static constexpr int DPB = (!wide && KR <= 4) ? 2 : 1;
+    static constexpr int QPB = wide ? 1 : 2;
+    static constexpr int DPB = wide ? 1 : 2;
     static constexpr int DG = DPB == 2 ? 2 : 4;
     static constexpr int QG = kProducers / DG;
     static constexpr int BQ = QG * QPB * 16;
@@ -437,8 +547,17 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
         // same for every candidate of a query and does not change its rank.
         // Scaled formats multiply q.y by the query's and the row's 1/scale.
         const int cw = wave - kProducers;
-        MultiSelect<KR, T, QW> sel;
-        sel.init(args.keff);
+        using Sel = typename std::conditional<S::mem_queues, GlobalSelect<KR, T, QW>,
+                                              MultiSelect<KR, T, QW>>::type;
+        Sel sel;
+        if constexpr (S::mem_queues) {
+            const int64_t qf = q0 + cw * QW;
+            const int64_t left = args.nq - qf;
+            sel.init(args.keff, args.part + (qf * args.nchunks + chunk) * KS,
+                     (int64_t)args.nchunks * KS, (int)(left < 0 ? 0 : left < QW ? left : QW));
+        } else {
+            sel.init(args.keff);
+        }
         float qs[QW];
 #pragma unroll
         for (int qq = 0; qq < QW; ++qq) {
@@ -491,13 +610,15 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
         }
         sel.finish();
         exchange_bounds(sel, args, q0 + cw * QW, lane);
+        if constexpr (!S::mem_queues) {
 #pragma unroll
-        for (int qq = 0; qq < QW; ++qq) {
-            const int64_t q = q0 + cw * QW + qq;
-            if (q < args.nq) {
-                uint64_t* out = args.part + (q * args.nchunks + chunk) * KS;
+            for (int qq = 0; qq < QW; ++qq) {
+                const int64_t q = q0 + cw * QW + qq;
+                if (q < args.nq) {
+                    uint64_t* out = args.part + (q * args.nchunks + chunk) * KS;
 #pragma unroll
-                for (int r = 0; r < KR; ++r) out[r * 64 + lane] = sel.key(qq, r);
+                    for (int r = 0; r < KR; ++r) out[r * 64 + lane] = sel.key(qq, r);
+                }
             }
         }
     }

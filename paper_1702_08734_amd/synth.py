@@ -142,7 +142,22 @@ def ivfpq_workload(nb: int = 10_000_000, nq: int = 10_000, nt: int = 500_000):
             "nprobes": (1, 8, 16, 32, 64, 128), "rerank": (256, 1024),
             "learn_rerank": 256, "learn_cap": 32, "learn_fixed_nprobes": tuple(range(1, 13)),
             "learn_train": 200_000, "learn_epochs": 10, "serve_requests": 2000,
-            "serve_load": (0.5, 0.8)}
+            "serve_load": (0.5, 0.8), "base": 103, "mix": (1000, 128, (103, 99))}
+
+
+def ivfpq_large_workload(nb: int = 50_000_000, nq: int = 10_000, nt: int = 500_000):
+    """Learned-probe and serving workload: 50,000,000 x 128 rows of a
+    1,000-component mixture, 16,384 coarse centroids, PQ 16 x 8 bit."""
+    mix = Mixture(1000, 128, (105, 99))
+    xb = mix.sample(nb, (105, 0))
+    xq = mix.sample(nq, (105, 1))
+    sample = choose_rows(nb, nt, (105, 2))
+    return {"xb": xb, "xq": xq, "sample": sample, "nlist": 16384, "M": 16,
+            "coarse_init": choose_rows(nt, 16384, (105, 3)),
+            "pq_init": pq_init_rows(nt, 16, (105, 4)), "k": 10,
+            "learn_rerank": 256, "learn_cap": 64, "learn_fixed_nprobes": tuple(range(1, 17)),
+            "learn_train": 200_000, "learn_epochs": 10, "serve_requests": 2000,
+            "serve_load": (0.5, 0.8), "base": 105, "mix": (1000, 128, (105, 99))}
 
 
 def lowp_workload(nb: int = 20_000_000, nq: int = 10_000):
