@@ -307,6 +307,30 @@ def learned_probe_section(api, synth, torch, ix, xb, xq, w, recalls):
         out.update({"ms": round(dt * 1e3, 3), "qps_learned": round(nq / dt, 1),
                     "recall_at_10": r1, "ten_intersection": r2,
                     "mean_nprobe": round(float(tau.float().mean().item()), 2)})
+    # device time per kernel of one search at the fixed count reaching 0.9 and
+    # of one learned search (the rest of the wall time is launches and syncs)
+    names = ("knn_fused", "knn_merge_rerank", "ivf_term3", "ivf_scan", "ivf_merge", "rerank",
+             "mlp_forward")
+
+    def breakdown(fn):
+        fn()
+        torch.cuda.synchronize()
+        api.profile_enable(True)
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        api.profile_enable(False)
+        b = {n: round(api.profile_read(n)[0], 3) for n in names}
+        b["wall_ms"] = round(wall * 1e3, 3)
+        return b
+
+    if best_fixed:
+        tau0 = min(c["nprobe"] for c in best_fixed)
+        out["fixed_breakdown_ms"] = breakdown(lambda: ix.search_rerank(xq, k, tau0, R, xb))
+    if delta is not None:
+        out["learned_breakdown_ms"] = breakdown(
+            lambda: ix.search_learned(net, delta, xq, k, cap, R, xb))
     out["net"] = net
     return out
 

@@ -371,18 +371,25 @@ constexpr int kBoundEvery = 32;
 template <class Sel>
 __device__ __forceinline__ void exchange_bounds(Sel& sel, const FusedArgs& a, int64_t qfirst,
                                                 int lane) {
+    constexpr int QW = Sel::kQueries;
     if (!a.bound) return;
+    // lane qq < QW handles query qfirst + qq: one load and one atomic per
+    // exchange for all of the consumer's queries
+    const int64_t q = qfirst + lane;
+    const bool mine_lane = lane < QW && q < a.nq;
+    uint32_t got = 0xFF800000u;  // order-mapped +inf
+    if (mine_lane) got = __hip_atomic_load(a.bound + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    float mine = INFINITY;
 #pragma unroll
-    for (int qq = 0; qq < Sel::kQueries; ++qq) {
-        const int64_t q = qfirst + qq;
-        if (q < a.nq) {
-            sel.bound(qq, order_float(__atomic_load_n(a.bound + q, __ATOMIC_RELAXED)));
-            const float mine = sel.kf[qq];
-            if (lane == 0 && mine < INFINITY)
-                __hip_atomic_fetch_min(a.bound + q, float_order(mine + 0.0f), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        }
+    for (int qq = 0; qq < QW; ++qq) {
+        if (qfirst + qq < a.nq)
+            sel.bound(qq, order_float((uint32_t)__builtin_amdgcn_readlane((int)got, qq)));
+        const float kq = sel.kf[qq];
+        mine = lane == qq ? kq : mine;
     }
+    if (mine_lane && mine < INFINITY)
+        __hip_atomic_fetch_min(a.bound + q, float_order(mine + 0.0f), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <class Op, int KR, int DP, bool VEC, bool L2>
@@ -490,7 +497,6 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
         for (int64_t s = 0; s <= nsteps; ++s) {
             if (s < nsteps) {
                 const int64_t ahead = s + NBUF - 1;
-                if (ahead < nsteps) load_tile(c0 + ahead * BN, (int)(ahead % NBUF));
                 const uint4* bt = btile[s % NBUF];
                 // All B granules of the step first, so that LDS latency
                 // overlaps the matrix work of earlier granules.
@@ -511,8 +517,21 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
                     for (int qb = 0; qb < QPB; ++qb)
 #pragma unroll
                         for (int db = 0; db < DPB; ++db) acc[kk][qb][db] = floatx4{0.f, 0.f, 0.f, 0.f};
+                // The tile loads two steps ahead are issued between the two
+                // halves of the matrix work, so their issue cost hides under it.
+                constexpr int H = S4 / 2;
 #pragma unroll
-                for (int s4 = 0; s4 < S4; ++s4)
+                for (int s4 = 0; s4 < H; ++s4)
+#pragma unroll
+                    for (int qb = 0; qb < QPB; ++qb)
+#pragma unroll
+                        for (int db = 0; db < DPB; ++db)
+                            acc[s4 % SK][qb][db] = Op::mma(acc[s4 % SK][qb][db], areg[qb][s4], b[s4][db]);
+                __builtin_amdgcn_sched_barrier(0);
+                if (ahead < nsteps) load_tile(c0 + ahead * BN, (int)(ahead % NBUF));
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int s4 = H; s4 < S4; ++s4)
 #pragma unroll
                     for (int qb = 0; qb < QPB; ++qb)
 #pragma unroll
@@ -637,15 +656,32 @@ inline mk_status clear_bounds(uint32_t* bound, int64_t nq, hipStream_t s) {
     return MK_OK;
 }
 
-// Chunking of the database: enough workgroups to fill the chip several times
-// over, chunks long enough (>= 32 queue lengths) that partial lists stay small.
+// Chunking of the database.  Every chunk a query's rows are split into costs
+// that query about keff insertions into its selector even with the shared
+// bound (and the first about keff (1 + ln(chunk / keff))), so long queues get
+// fewer, longer chunks: about 4 workgroups per CU for queues of 512+ entries,
+// 16 otherwise, chunks of at least 32 queue lengths, and among chunk counts
+// within 25% of that target the one whose last wave of workgroups is fullest.
 inline void plan_chunks(int64_t nq, int64_t nb, int BQ, int BN, int KS, int64_t* nqb,
                         int64_t* nchunks, int64_t* chunk_len) {
+    constexpr int64_t kCUs = 256;
     *nqb = ceil_div(nq, BQ);
-    int64_t want = ceil_div(4096, *nqb);
-    int64_t max_by_len = nb / (32 * KS) > 1 ? nb / (32 * KS) : 1;
-    int64_t nc = want < max_by_len ? want : max_by_len;
-    if (nc < 1) nc = 1;
+    const int64_t target = (KS >= 512 ? 4 : 16) * kCUs;
+    const int64_t want = ceil_div(target, *nqb);
+    const int64_t max_by_len = nb / (32 * KS) > 1 ? nb / (32 * KS) : 1;
+    int64_t hi = want < max_by_len ? want : max_by_len;
+    if (hi < 1) hi = 1;
+    int64_t lo = (hi * 3) / 4 > 1 ? (hi * 3) / 4 : 1;
+    int64_t nc = hi;
+    double best = -1.0;
+    for (int64_t c = hi; c >= lo; --c) {
+        const int64_t wgs = *nqb * c;
+        const double fill = (double)wgs / (double)(ceil_div(wgs, kCUs) * kCUs);
+        if (fill > best + 1e-9) {
+            best = fill;
+            nc = c;
+        }
+    }
     int64_t cl = ceil_div(ceil_div(nb, nc), BN) * BN;
     if (cl == 0) cl = BN;
     *chunk_len = cl;

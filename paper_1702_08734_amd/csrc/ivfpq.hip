@@ -814,9 +814,12 @@ mk_status scan_fixed(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t nprobe, 
     MK_TRY(part.alloc(sizeof(uint64_t) * nq * *ngroups * kk, s));
     MK_TRY(knn_search(xq, nq, ix->coarse, ix->coarse_norms, ix->nlist, ix->d, nprobe,
                       MK_METRIC_L2, cd.as<float>(), ci.as<int64_t>(), s));
-    hipLaunchKernelGGL(term3_kernel, dim3(grid_of(nq * M * 256)), dim3(kBlock), 0, s, xq, nq, M,
-                       ix->dsub, ix->books, t3.as<float>());
-    MK_LAUNCHED();
+    {
+        ProfScope prof("ivf_term3", s);
+        hipLaunchKernelGGL(term3_kernel, dim3(grid_of(nq * M * 256)), dim3(kBlock), 0, s, xq, nq,
+                           M, ix->dsub, ix->books, t3.as<float>());
+        MK_LAUNCHED();
+    }
     return launch_scan(t3.as<float>(), ix->t1e, cd.as<float>(), ci.as<int64_t>(), nprobe,
                        ix->offsets_dev, ix->codes, ix->ids, M, nq, G, kk, part.as<uint64_t>(),
                        nq * *ngroups, s);
@@ -903,7 +906,10 @@ mk_status search_learned(mk_ivfpq* ix, const mk_mlp* net, float delta, const flo
                        dim3(grid_of(nq * (ix->d + kProbeDists))), dim3(kBlock), 0, s, xq, nq,
                        ix->d, cd.as<float>(), cap, F.as<float>());
     MK_LAUNCHED();
-    MK_TRY(mlp_forward_dev(net, F.as<float>(), nq, yhat.as<float>(), s));
+    {
+        ProfScope prof("mlp_forward", s);
+        MK_TRY(mlp_forward_dev(net, F.as<float>(), nq, yhat.as<float>(), s));
+    }
     hipLaunchKernelGGL(probe_count_kernel, dim3(grid_of(nq)), dim3(kBlock), 0, s,
                        yhat.as<float>(), nq, delta, cap, tau.as<int32_t>(), cnt.as<int64_t>());
     MK_LAUNCHED();
@@ -935,9 +941,12 @@ mk_status search_learned(mk_ivfpq* ix, const mk_mlp* net, float delta, const flo
     MK_TRY(prefix(&nwork));
     MK_TRY(t3.alloc(sizeof(float) * nq * M * 256, s));
     MK_TRY(part.alloc(sizeof(uint64_t) * nwork * kk, s));
-    hipLaunchKernelGGL(term3_kernel, dim3(grid_of(nq * M * 256)), dim3(kBlock), 0, s, xq, nq, M,
-                       ix->dsub, ix->books, t3.as<float>());
-    MK_LAUNCHED();
+    {
+        ProfScope prof("ivf_term3", s);
+        hipLaunchKernelGGL(term3_kernel, dim3(grid_of(nq * M * 256)), dim3(kBlock), 0, s, xq, nq,
+                           M, ix->dsub, ix->books, t3.as<float>());
+        MK_LAUNCHED();
+    }
     MK_TRY(launch_scan(t3.as<float>(), ix->t1e, cd.as<float>(), ci.as<int64_t>(), cap,
                        ix->offsets_dev, ix->codes, ix->ids, M, nq, G, kk, part.as<uint64_t>(),
                        nwork, s, work.as<int64_t>(), tau.as<int32_t>()));
