@@ -356,7 +356,7 @@ mk_status mk_ivfpq_probe_labels(const mk_ivfpq* index, const float* xq, int64_t 
  * 32 <= cap <= min(nlist, 1024).  R = 0: ADC distances as in
  * mk_ivfpq_search; R >= k: exact re-rank of an R-entry short list against
  * xb [nb, d] as in mk_ivfpq_search_rerank.  nprobe_used [nq] int32 (may be
- * NULL) receives tau_q.  Synchronises once (to size the list-scan launch).
+ * NULL) receives tau_q.  Asynchronous like the other searches.
  */
 mk_status mk_ivfpq_search_learned(mk_ivfpq* index, const mk_mlp* net, float delta,
                                   const float* xq, int64_t nq, int32_t k, int32_t cap, int32_t R,

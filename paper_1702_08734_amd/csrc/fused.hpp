@@ -699,6 +699,8 @@ __global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
     constexpr int T = SelParams<KR>::T;
     constexpr int KS = 64 * KR;
     __shared__ __align__(16) float xs[kMergeWaves][kMaxDim];
+    __shared__ uint64_t kl[kMergeWaves][KS];
+    __shared__ float dist[kMergeWaves][KS];
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
     const int64_t q = (int64_t)blockIdx.x * kMergeWaves + wave;
@@ -721,6 +723,56 @@ __global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
 
     const float* x = xq + q * d;
     for (int t = lane; t < d; t += 64) xs[wave][t] = x[t];
+    // the kept keys, in list order, through LDS
+#pragma unroll
+    for (int r = 0; r < KR; ++r) kl[wave][r * 64 + lane] = ws.w[r];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+
+    // FP32 direct-form distances of the first keff keys: 16 lanes per row and
+    // 4 rows per pass, each lane summing every 16th 16-byte granule of the
+    // row (coalesced), then a 16-lane reduction
+    const int sub = lane & 15, rsel = lane >> 4;
+    const float* xw = xs[wave];
+#pragma unroll 1
+    for (int e0 = 0; e0 < keff; e0 += 4) {
+        const int e = e0 + rsel;
+        const uint64_t key = e < keff ? kl[wave][e] : kSentinel;
+        float sacc = 0.f;
+        if (key != kSentinel) {
+            const float* y = xb + (int64_t)key_index(key) * d;
+            if (vec) {
+                for (int t = 4 * sub; t < d; t += 64) {
+                    const float4 yv = *reinterpret_cast<const float4*>(y + t);
+                    const float4 xv = *reinterpret_cast<const float4*>(xw + t);
+                    if (l2) {
+                        const float a = xv.x - yv.x, b = xv.y - yv.y, c = xv.z - yv.z, dd = xv.w - yv.w;
+                        sacc = fmaf(a, a, sacc);
+                        sacc = fmaf(b, b, sacc);
+                        sacc = fmaf(c, c, sacc);
+                        sacc = fmaf(dd, dd, sacc);
+                    } else {
+                        sacc = fmaf(xv.x, yv.x, sacc);
+                        sacc = fmaf(xv.y, yv.y, sacc);
+                        sacc = fmaf(xv.z, yv.z, sacc);
+                        sacc = fmaf(xv.w, yv.w, sacc);
+                    }
+                }
+            } else {
+                for (int t = sub; t < d; t += 16) {
+                    if (l2) {
+                        const float a = xw[t] - y[t];
+                        sacc = fmaf(a, a, sacc);
+                    } else {
+                        sacc = fmaf(xw[t], y[t], sacc);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) sacc += __shfl_xor(sacc, o, 16);
+        if (sub == 0 && e < keff) dist[wave][e] = sacc;
+    }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
 
@@ -731,37 +783,8 @@ __global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
         const int e = r * 64 + lane;
         nk[r] = kSentinel;
         if (key != kSentinel && e < keff) {
-            const uint32_t i = key_index(key);
-            const float* y = xb + (int64_t)i * d;
-            float s = 0.f;
-            if (vec) {
-                for (int t = 0; t < d; t += 4) {
-                    const float4 yv = *reinterpret_cast<const float4*>(y + t);
-                    const float4 xv = *reinterpret_cast<const float4*>(&xs[wave][t]);
-                    if (l2) {
-                        float a = xv.x - yv.x, b = xv.y - yv.y, c = xv.z - yv.z, dd = xv.w - yv.w;
-                        s = fmaf(a, a, s);
-                        s = fmaf(b, b, s);
-                        s = fmaf(c, c, s);
-                        s = fmaf(dd, dd, s);
-                    } else {
-                        s = fmaf(xv.x, yv.x, s);
-                        s = fmaf(xv.y, yv.y, s);
-                        s = fmaf(xv.z, yv.z, s);
-                        s = fmaf(xv.w, yv.w, s);
-                    }
-                }
-            } else {
-                for (int t = 0; t < d; ++t) {
-                    if (l2) {
-                        const float a = xs[wave][t] - y[t];
-                        s = fmaf(a, a, s);
-                    } else {
-                        s = fmaf(xs[wave][t], y[t], s);
-                    }
-                }
-            }
-            nk[r] = make_key(l2 ? s : -s, i);
+            const float sv = dist[wave][e];
+            nk[r] = make_key(l2 ? sv : -sv, key_index(key));
         }
     }
     bitonic_sort<false, KR>(nk);

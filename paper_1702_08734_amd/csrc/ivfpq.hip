@@ -312,17 +312,59 @@ __global__ void term1_kernel(const float* __restrict__ coarse, const float* __re
 }
 
 // term3[q, m, j] = <x_q^m, c_{m,j}>   (Eq. 11, term 3)
-__global__ void term3_kernel(const float* __restrict__ xq, int64_t nq, int32_t M, int32_t ds,
-                             const float* __restrict__ books, float* __restrict__ term3) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= nq * M * 256) return;
-    const int64_t q = g / (M * 256);
-    const int32_t m = (int32_t)((g / 256) % M), j = (int32_t)(g % 256);
-    const float* cw = books + ((int64_t)m * 256 + j) * ds;
-    const float* x = xq + q * (int64_t)M * ds + (int64_t)m * ds;
-    float ip = 0.f;
-    for (int t = 0; t < ds; ++t) ip = fmaf(x[t], cw[t], ip);
-    term3[g] = ip;
+// term3[q][m][j] = <x_q^m, c_{m,j}> (Eq. 11).  One workgroup per (tile of
+// kT3Queries queries, sub-quantizer m), thread j owns codeword j; the
+// codebook and the queries' sub-vectors pass through LDS in slices of 16
+// components (summed in component order), and each query's 256 outputs are
+// written as one coalesced row.
+constexpr int kT3Queries = 16;
+
+__global__ __launch_bounds__(256) void term3_kernel(const float* __restrict__ xq, int64_t nq,
+                                                    int32_t M, int32_t ds,
+                                                    const float* __restrict__ books,
+                                                    float* __restrict__ term3) {
+    __shared__ float cb[256][17];
+    __shared__ float xs[kT3Queries][16];
+    const int64_t q0 = (int64_t)blockIdx.x * kT3Queries;
+    const int32_t m = blockIdx.y;
+    const int j = threadIdx.x;
+    const int d = M * ds;
+    float acc[kT3Queries];
+#pragma unroll
+    for (int i = 0; i < kT3Queries; ++i) acc[i] = 0.f;
+    for (int t0 = 0; t0 < ds; t0 += 16) {
+        const int w = ds - t0 < 16 ? ds - t0 : 16;
+        for (int e = j; e < 256 * 16; e += 256) {
+            const int jj = e / 16, t = e % 16;
+            cb[jj][t] = t < w ? books[((int64_t)m * 256 + jj) * ds + t0 + t] : 0.f;
+        }
+        for (int e = j; e < kT3Queries * 16; e += 256) {
+            const int i = e / 16, t = e % 16;
+            const int64_t q = q0 + i;
+            xs[i][t] = (t < w && q < nq) ? xq[q * d + (int64_t)m * ds + t0 + t] : 0.f;
+        }
+        __syncthreads();
+        for (int t = 0; t < w; ++t) {
+            const float c = cb[j][t];
+#pragma unroll
+            for (int i = 0; i < kT3Queries; ++i) acc[i] = fmaf(xs[i][t], c, acc[i]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < kT3Queries; ++i) {
+        const int64_t q = q0 + i;
+        if (q < nq) term3[(q * M + m) * 256 + j] = acc[i];
+    }
+}
+
+mk_status launch_term3(const float* xq, int64_t nq, int32_t M, int32_t ds, const float* books,
+                       float* term3, hipStream_t s) {
+    if (nq == 0) return MK_OK;
+    hipLaunchKernelGGL(term3_kernel, dim3((unsigned)ceil_div(nq, kT3Queries), (unsigned)M),
+                       dim3(256), 0, s, xq, nq, M, ds, books, term3);
+    MK_LAUNCHED();
+    return MK_OK;
 }
 
 __global__ void histogram_kernel(const int64_t* __restrict__ list, int64_t n,
@@ -488,6 +530,7 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
     int64_t q, g;
     int32_t np;
     if (work) {
+        if (item >= work[nq]) return;  // grid sized for the largest possible count
         int64_t lo = 0, hi = nq;  // largest q with work[q] <= item
         while (hi - lo > 1) {
             const int64_t mid = (lo + hi) >> 1;
@@ -816,9 +859,7 @@ mk_status scan_fixed(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t nprobe, 
                       MK_METRIC_L2, cd.as<float>(), ci.as<int64_t>(), s));
     {
         ProfScope prof("ivf_term3", s);
-        hipLaunchKernelGGL(term3_kernel, dim3(grid_of(nq * M * 256)), dim3(kBlock), 0, s, xq, nq,
-                           M, ix->dsub, ix->books, t3.as<float>());
-        MK_LAUNCHED();
+        MK_TRY(launch_term3(xq, nq, M, ix->dsub, ix->books, t3.as<float>(), s));
     }
     return launch_scan(t3.as<float>(), ix->t1e, cd.as<float>(), ci.as<int64_t>(), nprobe,
                        ix->offsets_dev, ix->codes, ix->ids, M, nq, G, kk, part.as<uint64_t>(),
@@ -915,41 +956,32 @@ mk_status search_learned(mk_ivfpq* ix, const mk_mlp* net, float delta, const flo
     MK_LAUNCHED();
     if (used)
         MK_HIP(hipMemcpyAsync(used, tau.ptr, sizeof(int32_t) * nq, hipMemcpyDeviceToDevice, s));
-    // exclusive prefix sums of per-query counts: work[0] = 0, work[q + 1] =
-    // cnt[0] + ... + cnt[q]; returns the total (synchronises)
+    // workgroups per query ceil(tau / G) and their exclusive prefix sums
+    // work[0] = 0, work[q + 1] = cnt[0] + ... + cnt[q], all on the device; the
+    // scan grid is sized for tau = cap everywhere and the surplus workgroups
+    // return at once, so the search never waits for the host
+    const int32_t G = scan_group(nq * (int64_t)(cap < 8 ? cap : 8));
+    const int64_t max_items = nq * ceil_div(cap, G);
+    hipLaunchKernelGGL(group_count_kernel, dim3(grid_of(nq)), dim3(kBlock), 0, s,
+                       tau.as<int32_t>(), nq, G, cnt.as<int64_t>());
+    MK_LAUNCHED();
+    hipLaunchKernelGGL(zero_first_kernel, dim3(1), dim3(1), 0, s, work.as<int64_t>());
+    MK_LAUNCHED();
     size_t tmp_bytes = 0;
     MK_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, cnt.as<int64_t>(),
                                             work.as<int64_t>() + 1, (int)nq, s));
     MK_TRY(tmp.alloc(tmp_bytes, s));
-    auto prefix = [&](int64_t* total) -> mk_status {
-        hipLaunchKernelGGL(zero_first_kernel, dim3(1), dim3(1), 0, s, work.as<int64_t>());
-        MK_LAUNCHED();
-        MK_HIP(hipcub::DeviceScan::InclusiveSum(tmp.ptr, tmp_bytes, cnt.as<int64_t>(),
-                                                work.as<int64_t>() + 1, (int)nq, s));
-        MK_HIP(hipMemcpyAsync(total, work.as<int64_t>() + nq, sizeof(int64_t),
-                              hipMemcpyDeviceToHost, s));
-        MK_HIP(hipStreamSynchronize(s));
-        return MK_OK;
-    };
-    int64_t probes = 0, nwork = 0;
-    MK_TRY(prefix(&probes));
-    // lists per workgroup from the total probe count, then workgroups per query
-    const int32_t G = scan_group(probes);
-    hipLaunchKernelGGL(group_count_kernel, dim3(grid_of(nq)), dim3(kBlock), 0, s,
-                       tau.as<int32_t>(), nq, G, cnt.as<int64_t>());
-    MK_LAUNCHED();
-    MK_TRY(prefix(&nwork));
+    MK_HIP(hipcub::DeviceScan::InclusiveSum(tmp.ptr, tmp_bytes, cnt.as<int64_t>(),
+                                            work.as<int64_t>() + 1, (int)nq, s));
     MK_TRY(t3.alloc(sizeof(float) * nq * M * 256, s));
-    MK_TRY(part.alloc(sizeof(uint64_t) * nwork * kk, s));
+    MK_TRY(part.alloc(sizeof(uint64_t) * max_items * kk, s));
     {
         ProfScope prof("ivf_term3", s);
-        hipLaunchKernelGGL(term3_kernel, dim3(grid_of(nq * M * 256)), dim3(kBlock), 0, s, xq, nq,
-                           M, ix->dsub, ix->books, t3.as<float>());
-        MK_LAUNCHED();
+        MK_TRY(launch_term3(xq, nq, M, ix->dsub, ix->books, t3.as<float>(), s));
     }
     MK_TRY(launch_scan(t3.as<float>(), ix->t1e, cd.as<float>(), ci.as<int64_t>(), cap,
                        ix->offsets_dev, ix->codes, ix->ids, M, nq, G, kk, part.as<uint64_t>(),
-                       nwork, s, work.as<int64_t>(), tau.as<int32_t>()));
+                       max_items, s, work.as<int64_t>(), tau.as<int32_t>()));
     if (R <= 0) {
         ProfScope prof("ivf_merge", s);
         return merge_key_lists(part.as<uint64_t>(), nq, 0, k, D, I, s, nullptr,
