@@ -247,14 +247,30 @@ __global__ void out_backward_kernel(const float* __restrict__ dy, const float* _
     dZ2[e] = H2[e] > 0.f ? dy[m] * w3[j] : 0.f;
 }
 
-// out[j] = sum_m wgt[m] X[m][j] (wgt optional), fixed order over m.
-__global__ void colsum_kernel(const float* __restrict__ X, int64_t B, int32_t N,
-                              const float* __restrict__ wgt, float* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+// out[j] = sum_m wgt[m] X[m][j] (wgt optional).  A workgroup takes 64 columns;
+// its 16 row groups each sum every 16th row, then a fixed tree adds the 16
+// partial sums (the same order on every call).
+constexpr int kColRows = 16;
+
+__global__ __launch_bounds__(64 * kColRows) void colsum_kernel(const float* __restrict__ X,
+                                                               int64_t B, int32_t N,
+                                                               const float* __restrict__ wgt,
+                                                               float* __restrict__ out) {
+    __shared__ float part[kColRows][64];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
     float s = 0.f;
-    for (int64_t m = 0; m < B; ++m) s = wgt ? fmaf(wgt[m], X[m * N + j], s) : s + X[m * N + j];
-    out[j] = s;
+    if (j < N) {
+        for (int64_t m = g; m < B; m += kColRows)
+            s = wgt ? fmaf(wgt[m], X[m * N + j], s) : s + X[m * N + j];
+    }
+    part[g][c] = s;
+    __syncthreads();
+    for (int w = kColRows / 2; w >= 1; w >>= 1) {
+        if (g < w) part[g][c] += part[g + w][c];
+        __syncthreads();
+    }
+    if (g == 0 && j < N) out[j] = part[0][c];
 }
 
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
@@ -270,23 +286,44 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
     p[i] -= lr * (a / bc1) / (sqrtf(b / bc2) + eps);
 }
 
-// Column mean and population standard deviation in FP64 (zero spread -> 1).
-__global__ void stats_kernel(const float* __restrict__ F, int64_t n, int32_t din,
-                             float* __restrict__ mean, float* __restrict__ inv_std) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= din) return;
+// Column mean and population standard deviation in FP64 (zero spread -> 1):
+// a workgroup per 64 columns, 16 row groups and a fixed tree, two passes.
+__global__ __launch_bounds__(64 * kColRows) void stats_kernel(const float* __restrict__ F,
+                                                              int64_t n, int32_t din,
+                                                              float* __restrict__ mean,
+                                                              float* __restrict__ inv_std) {
+    __shared__ double part[kColRows][64];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int t = blockIdx.x * 64 + c;
     double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += (double)F[i * din + t];
-    const double mu = s / (double)n;
-    double v = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        const double d = (double)F[i * din + t] - mu;
-        v += d * d;
+    if (t < din)
+        for (int64_t i = g; i < n; i += kColRows) s += (double)F[i * din + t];
+    part[g][c] = s;
+    __syncthreads();
+    for (int w = kColRows / 2; w >= 1; w >>= 1) {
+        if (g < w) part[g][c] += part[g + w][c];
+        __syncthreads();
     }
-    double sd = sqrt(v / (double)n);
-    if (sd == 0.0) sd = 1.0;
-    mean[t] = (float)mu;
-    inv_std[t] = (float)(1.0 / sd);
+    const double mu = part[0][c] / (double)n;
+    __syncthreads();
+    double v = 0.0;
+    if (t < din)
+        for (int64_t i = g; i < n; i += kColRows) {
+            const double d = (double)F[i * din + t] - mu;
+            v += d * d;
+        }
+    part[g][c] = v;
+    __syncthreads();
+    for (int w = kColRows / 2; w >= 1; w >>= 1) {
+        if (g < w) part[g][c] += part[g + w][c];
+        __syncthreads();
+    }
+    if (g == 0 && t < din) {
+        double sd = sqrt(part[0][c] / (double)n);
+        if (sd == 0.0) sd = 1.0;
+        mean[t] = (float)mu;
+        inv_std[t] = (float)(1.0 / sd);
+    }
 }
 
 // Work buffers of one pass over B rows.
@@ -347,12 +384,13 @@ mk_status backward(mk_mlp* net, const float* y, const int64_t* rows, int64_t B, 
                        p.dz2.as<float>());
     MK_LAUNCHED();
     // g_w3 = h2^T dy, g_b3 = sum dy, g_b2 = column sums of dz2
-    hipLaunchKernelGGL(colsum_kernel, dim3(grid_of(h)), dim3(kBlock), 0, s, p.h2.as<float>(), B,
-                       net->h, p.dy.as<float>(), G + L.w3);
-    hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(kBlock), 0, s, p.dy.as<float>(), B, 1,
+    const dim3 cgrid((unsigned)ceil_div(h, 64)), cblock(64 * kColRows);
+    hipLaunchKernelGGL(colsum_kernel, cgrid, cblock, 0, s, p.h2.as<float>(), B, net->h,
+                       p.dy.as<float>(), G + L.w3);
+    hipLaunchKernelGGL(colsum_kernel, dim3(1), cblock, 0, s, p.dy.as<float>(), B, 1,
                        (const float*)nullptr, G + L.b3);
-    hipLaunchKernelGGL(colsum_kernel, dim3(grid_of(h)), dim3(kBlock), 0, s, p.dz2.as<float>(), B,
-                       net->h, (const float*)nullptr, G + L.b2);
+    hipLaunchKernelGGL(colsum_kernel, cgrid, cblock, 0, s, p.dz2.as<float>(), B, net->h,
+                       (const float*)nullptr, G + L.b2);
     MK_LAUNCHED();
     // g_W2 = dz2^T h1
     MK_TRY(gemm(net, gemm_args(p.dz2.as<float>(), 1, h, p.h1.as<float>(), h, 1, G + L.W2, h, h, h, B),
@@ -363,8 +401,8 @@ mk_status backward(mk_mlp* net, const float* y, const int64_t* rows, int64_t B, 
     gd.mask = p.h1.as<float>();
     gd.ldm = h;
     MK_TRY(gemm(net, gd, s));
-    hipLaunchKernelGGL(colsum_kernel, dim3(grid_of(h)), dim3(kBlock), 0, s, p.dz1.as<float>(), B,
-                       net->h, (const float*)nullptr, G + L.b1);
+    hipLaunchKernelGGL(colsum_kernel, cgrid, cblock, 0, s, p.dz1.as<float>(), B, net->h,
+                       (const float*)nullptr, G + L.b1);
     MK_LAUNCHED();
     // g_W1 = dz1^T Xs
     MK_TRY(gemm(net, gemm_args(p.dz1.as<float>(), 1, h, p.xs.as<float>(), din, 1, G + L.W1, din, h,
@@ -479,8 +517,9 @@ extern "C" mk_status mk_mlp_fit_standardization(mk_mlp* net, const float* F, int
                                                 mk_stream_t stream) {
     MK_REQUIRE(net && F, MK_ERR_INVALID_ARG, "null pointer");
     MK_REQUIRE(n >= 1, MK_ERR_INVALID_ARG, "need n >= 1");
-    hipLaunchKernelGGL(mk::stats_kernel, dim3(mk::grid_of(net->din)), dim3(mk::kBlock), 0,
-                       static_cast<hipStream_t>(stream), F, n, net->din, net->mean, net->inv_std);
+    hipLaunchKernelGGL(mk::stats_kernel, dim3((unsigned)mk::ceil_div(net->din, 64)),
+                       dim3(64 * mk::kColRows), 0, static_cast<hipStream_t>(stream), F, n, net->din,
+                       net->mean, net->inv_std);
     MK_LAUNCHED();
     return MK_OK;
 }

@@ -141,7 +141,7 @@ def ivfpq_workload(nb: int = 10_000_000, nq: int = 10_000, nt: int = 500_000):
             "pq_init": pq_init_rows(nt, 16, (103, 4)), "k": 100,
             "nprobes": (1, 8, 16, 32, 64, 128), "rerank": (256, 1024),
             "learn_rerank": 256, "learn_cap": 32, "learn_fixed_nprobes": tuple(range(1, 13)),
-            "learn_train": 200_000, "learn_epochs": 100, "serve_requests": 2000,
+            "learn_train": 200_000, "learn_epochs": 30, "serve_requests": 2000,
             "serve_load": (0.5, 0.8), "base": 103, "mix": (1000, 128, (103, 99))}
 
 
@@ -156,7 +156,7 @@ def ivfpq_large_workload(nb: int = 50_000_000, nq: int = 10_000, nt: int = 500_0
             "coarse_init": choose_rows(nt, 16384, (105, 3)),
             "pq_init": pq_init_rows(nt, 16, (105, 4)), "k": 10,
             "learn_rerank": 256, "learn_cap": 64, "learn_fixed_nprobes": tuple(range(1, 17)),
-            "learn_train": 200_000, "learn_epochs": 100, "serve_requests": 2000,
+            "learn_train": 200_000, "learn_epochs": 30, "serve_requests": 2000,
             "serve_load": (0.5, 0.8), "base": 105, "mix": (1000, 128, (105, 99))}
 
 
