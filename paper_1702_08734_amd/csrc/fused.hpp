@@ -128,76 +128,165 @@ struct MultiSelect {
     }
 };
 
+// Chunks of one query tell each other how good their candidates are.  A
+// chunk that holds r candidates scoring at most v proves that r rows of the
+// database do; rows of different chunks are distinct, so once the proofs of
+// all chunks add up to keff rows scoring at most t, no candidate scoring
+// above t can enter the query's result.  Each chunk publishes four such
+// points (v at ranks r0, 2 r0, 4 r0 and keff of its queue, r0 = ceil(keff /
+// nchunks)); the tightest t that the published points prove is the query's
+// bound, which is near the keff-th score of everything its chunks have seen
+// so far, not merely of the best single chunk.
+constexpr int kRankPoints = 4;
+constexpr int kMaxRankChunks = 16;  // chunks per query when queues live in memory
+constexpr uint32_t kNoBound = 0xFFFFFFFFu;
+
 // QW selectors whose wave queues (64*KR keys per query, lane-stride) live in
 // device memory -- the kernel's own partial-result rows -- instead of
-// registers: only the dense thread-queue buffers and the per-query k-th keys
-// stay in registers, so one consumer can serve as many queries for 256- and
-// 1024-entry queues as for short ones.  A merge loads the query's wave
-// queue (each lane its own keys, so a lane only ever reads what it wrote),
-// merges the buffer in, and stores it back.  Queries at or beyond nvalid
-// never take candidates and are never written.
-template <int KR, int T, int QW>
+// registers: only the dense thread-queue buffers and the per-query
+// thresholds stay in registers, so one consumer can serve as many queries for
+// 256- and 1024-entry queues as for short ones.  A full buffer is not merged
+// at once: it is stored as one run of a pool of PR/T runs behind the queue,
+// and only a full pool is merged (sorted, PR registers, and merged into the
+// queue keeping the keff smallest), so the cost of the 64*KR-wide merge
+// network is shared by up to 64*PR candidates instead of 64*T.  The
+// admission threshold is then refreshed less often; it stays a valid filter
+// (the queue's keff-th key only decreases).  Each lane only ever reads back
+// what it wrote itself.  A merge publishes the queue's rank points (above).
+// Queries at or beyond nvalid never take candidates and are never written.
+template <int KR, int T, int QW, int PR>
 struct GlobalSelect {
     static constexpr int kQueries = QW;
+    static constexpr int kRuns = PR / T;  // buffers per pool
+    static_assert(PR % T == 0 && PR <= KR, "pool of whole buffers, at most a queue long");
     typedef uint32_t vq __attribute__((ext_vector_type(QW)));
     typedef float vqf __attribute__((ext_vector_type(QW)));
     vq tl[T], th[T];     // thread-queue buffers
-    vq kl, kh;           // key of each query's current k-th entry (wave-uniform)
-    vqf kf;              // its score, or the bound below if that is smaller
-    vqf bd;              // score bound from other database chunks
-    int cnt[QW];
+    vq kl, kh;           // admission threshold key of each query (wave-uniform)
+    vqf kf;              // its score
+    vq bdu;              // order-mapped score bound from the chunks' rank points
+    int cnt[QW];         // keys in each query's buffer
+    int runs[QW];        // buffers stored in each query's pool
     uint32_t stored;     // bit q: query q's queue in memory holds merged keys
-    uint64_t* wbase;     // queue of query q at wbase + q * wstride
+    uint64_t* wbase;     // queue of query q at wbase + q * wstride, its pool right after
     int64_t wstride;
+    uint32_t* rpub;      // rank points of query q, this chunk, at rpub + q * rstride
+    int64_t rstride;
+    int rank[kRankPoints];
     int keff, nvalid;
 
-    __device__ __forceinline__ void init(int k_eff, uint64_t* base, int64_t stride, int valid) {
+    __device__ __forceinline__ void init(int k_eff, uint64_t* base, int64_t stride, int valid,
+                                         uint32_t* rank_base, int nchunks) {
         keff = k_eff;
         wbase = base;
         wstride = stride;
         nvalid = valid;
+        rpub = rank_base;
+        rstride = (int64_t)nchunks * kRankPoints;
+        const int r0 = (k_eff + nchunks - 1) / nchunks;
+        rank[0] = r0;
+        rank[1] = 2 * r0 < k_eff ? 2 * r0 : k_eff;
+        rank[2] = 4 * r0 < k_eff ? 4 * r0 : k_eff;
+        rank[3] = k_eff;
 #pragma unroll
         for (int i = 0; i < T; ++i) tl[i] = th[i] = ~0u;
         kl = kh = ~0u;
         kf = INFINITY;
-        bd = INFINITY;
+        bdu = kNoBound;
 #pragma unroll
         for (int q = 0; q < QW; ++q) {
             cnt[q] = 0;
-            if (q >= valid) kf[q] = -INFINITY;
+            runs[q] = 0;
+            if (q >= valid) {  // never admits a candidate
+                kf[q] = -INFINITY;
+                kl[q] = kh[q] = 0u;
+            }
         }
         stored = 0;
     }
 
-    __device__ __forceinline__ void bound(int q, float b) {
-        bd[q] = fminf(bd[q], b);
-        kf[q] = fminf(kf[q], b);
+    // Lower query q's admission threshold to its queue's k-th key kk or the
+    // bound, whichever is smaller; a candidate scoring exactly the bound
+    // still competes (its key is below the bound's key for any index).
+    __device__ __forceinline__ void set_threshold(int q, uint64_t kk) {
+        const uint64_t bk = ((uint64_t)bdu[q] << 32) | 0xFFFFFFFFull;
+        const uint64_t th_key = kk < bk ? kk : bk;
+        kl[q] = (uint32_t)th_key;
+        kh[q] = (uint32_t)(th_key >> 32);
+        const uint32_t hi = (uint32_t)(th_key >> 32);
+        kf[q] = fminf(kf[q], hi == kNoBound ? INFINITY : order_float(hi));
     }
 
-    __device__ __forceinline__ void merge_slot(int q) {
+    __device__ __forceinline__ void bound_u(int q, uint32_t b) {
+        if (b < bdu[q]) {
+            bdu[q] = b;
+            set_threshold(q, ((uint64_t)kh[q] << 32) | kl[q]);
+        }
+    }
+
+    // Merge the first nruns buffers of query q's pool into its queue.
+    __device__ __forceinline__ void merge_pool(int q, int nruns) {
         const int lane = lane_id();
         uint64_t* wp = wbase + (int64_t)q * wstride;
+        const uint64_t* pp = wp + 64 * KR;
         const bool have = (stored >> q) & 1u;
-        uint64_t ww[KR], tt[T];
+        uint64_t ww[KR], pv[PR];
 #pragma unroll
         for (int r = 0; r < KR; ++r) ww[r] = have ? wp[r * 64 + lane] : kSentinel;
 #pragma unroll
-        for (int i = 0; i < T; ++i) tt[i] = ((uint64_t)th[i][q] << 32) | tl[i][q];
-        ws_merge<KR, T>(ww, tt);
+        for (int r = 0; r < PR; ++r) pv[r] = r / T < nruns ? pp[r * 64 + lane] : kSentinel;
+        ws_merge<KR, PR>(ww, pv);
         const uint64_t kk = ws_element<KR>(ww, keff - 1);
 #pragma unroll
         for (int r = 0; r < KR; ++r) wp[r * 64 + lane] = ww[r];
         stored |= 1u << q;
-#pragma unroll
-        for (int i = 0; i < T; ++i) {
-            tl[i][q] = ~0u;
-            th[i][q] = ~0u;
+        if (rpub) {
+            // the queue is sorted: its entry at rank r scores at most the
+            // published value, as do the r - 1 before it
+            const uint32_t p0 = (uint32_t)(ws_element<KR>(ww, rank[0] - 1) >> 32);
+            const uint32_t p1 = (uint32_t)(ws_element<KR>(ww, rank[1] - 1) >> 32);
+            const uint32_t p2 = (uint32_t)(ws_element<KR>(ww, rank[2] - 1) >> 32);
+            const uint32_t p3 = (uint32_t)(kk >> 32);
+            if (lane == 0) {
+                uint64_t* rp = reinterpret_cast<uint64_t*>(rpub + (int64_t)q * rstride);
+                __hip_atomic_store(rp, ((uint64_t)p1 << 32) | p0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(rp + 1, ((uint64_t)p3 << 32) | p2, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
 #pragma unroll
-        for (int qq = 0; qq < QW; ++qq) cnt[qq] = qq == q ? 0 : cnt[qq];
-        kl[q] = (uint32_t)kk;
-        kh[q] = (uint32_t)(kk >> 32);
-        kf[q] = fminf(kk == kSentinel ? INFINITY : key_score(kk), bd[q]);
+        for (int qq = 0; qq < QW; ++qq) runs[qq] = qq == q ? 0 : runs[qq];
+        set_threshold(q, kk);
+    }
+
+    // Store query q's buffer as the next run of its pool and empty it; merge
+    // the pool once it is full (or when `last`).
+    __device__ __forceinline__ void flush(int q, bool last) {
+        const int lane = lane_id();
+        int r = 0;
+#pragma unroll
+        for (int qq = 0; qq < QW; ++qq) r = qq == q ? runs[qq] : r;
+        int c = 0;
+#pragma unroll
+        for (int qq = 0; qq < QW; ++qq) c = qq == q ? cnt[qq] : c;
+        if (c > 0) {
+            uint64_t* pp = wbase + (int64_t)q * wstride + 64 * KR + (int64_t)r * 64 * T;
+#pragma unroll
+            for (int i = 0; i < T; ++i) pp[i * 64 + lane] = ((uint64_t)th[i][q] << 32) | tl[i][q];
+#pragma unroll
+            for (int i = 0; i < T; ++i) {
+                tl[i][q] = ~0u;
+                th[i][q] = ~0u;
+            }
+            r += 1;
+#pragma unroll
+            for (int qq = 0; qq < QW; ++qq) {
+                cnt[qq] = qq == q ? 0 : cnt[qq];
+                runs[qq] = qq == q ? r : runs[qq];
+            }
+        }
+        if (r == kRuns || last) merge_pool(q, r);
     }
 
     __device__ __forceinline__ void offer(const float (&score)[QW], uint32_t idx, bool ok) {
@@ -226,7 +315,7 @@ struct GlobalSelect {
         while (full) {
             const int q = __builtin_ctz(full);
             full &= full - 1;
-            merge_slot(q);
+            flush(q, false);
         }
     }
 
@@ -234,7 +323,83 @@ struct GlobalSelect {
     // of a query that never took a candidate).
     __device__ __forceinline__ void finish() {
 #pragma unroll 1
-        for (int q = 0; q < nvalid; ++q) merge_slot(q);
+        for (int q = 0; q < nvalid; ++q) flush(q, true);
+    }
+
+    // Tighten every query's bound from the rank points all chunks have
+    // published (bound[q][c][0..3], at most kMaxRankChunks chunks).  G lanes
+    // serve one query: lane m proposes the points of chunks m, m + G, ... as
+    // bounds and counts, over every chunk, the rows each proposal is proven
+    // for; the smallest proposal proven for keff rows wins.
+    __device__ __forceinline__ void exchange(const uint32_t* bound, int nchunks, int64_t qfirst,
+                                             int64_t nq) {
+        constexpr int G = 64 / QW;
+        constexpr int CPL = kMaxRankChunks / G > 0 ? kMaxRankChunks / G : 1;
+        static_assert(G * QW == 64, "one query per G lanes");
+        const int lane = lane_id();
+        const int qq = lane / G, m = lane % G;
+        const int64_t q = qfirst + qq;
+        const bool qok = q < nq;
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(bound + (qok ? q : 0) * rstride);
+        uint32_t cand[CPL][kRankPoints];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+            const int c = m + G * u;
+            uint64_t lo = ~0ull, hi = ~0ull;
+            if (qok && c < nchunks) {
+                lo = __hip_atomic_load(src + 2 * c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                hi = __hip_atomic_load(src + 2 * c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            cand[u][0] = (uint32_t)lo;
+            cand[u][1] = (uint32_t)(lo >> 32);
+            cand[u][2] = (uint32_t)hi;
+            cand[u][3] = (uint32_t)(hi >> 32);
+        }
+        int rows[CPL][kRankPoints];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u)
+#pragma unroll
+            for (int j = 0; j < kRankPoints; ++j) rows[u][j] = 0;
+        // chunk c's points are held by lane (qq * G + c % G), slot c / G
+#pragma unroll
+        for (int c = 0; c < kMaxRankChunks; ++c) {
+            if (c < nchunks) {
+                const int from = qq * G + c % G;
+                uint32_t v[kRankPoints];
+#pragma unroll
+                for (int j = 0; j < kRankPoints; ++j)
+                    v[j] = (uint32_t)__shfl((int)cand[c / G][j], from);
+#pragma unroll
+                for (int u = 0; u < CPL; ++u) {
+                    if (G * u < nchunks) {
+#pragma unroll
+                        for (int j = 0; j < kRankPoints; ++j) {
+                            const uint32_t t = cand[u][j];
+                            const int add = v[3] <= t   ? rank[3]
+                                            : v[2] <= t ? rank[2]
+                                            : v[1] <= t ? rank[1]
+                                            : v[0] <= t ? rank[0]
+                                                        : 0;
+                            rows[u][j] += add;
+                        }
+                    }
+                }
+            }
+        }
+        uint32_t best = kNoBound;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u)
+#pragma unroll
+            for (int j = 0; j < kRankPoints; ++j)
+                if (rows[u][j] >= keff && cand[u][j] < best) best = cand[u][j];
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            const uint32_t other = (uint32_t)__shfl_xor((int)best, o);
+            best = other < best ? other : best;
+        }
+#pragma unroll
+        for (int j = 0; j < QW; ++j)
+            if (qfirst + j < nq) bound_u(j, (uint32_t)__builtin_amdgcn_readlane((int)best, j * G));
     }
 };
 
@@ -326,13 +491,19 @@ constexpr int waitcnt_vm() {
 // consumer QW = BQ/4 queries.  BQ = 64, or 16 for rows over 512 bytes (LDS).
 constexpr int kProducers = 4;
 
+// Queues of 256 entries and more live in device memory (GlobalSelect).
+constexpr bool queues_in_memory(int KR) { return KR >= 4; }
+
 template <int KR, int RB>
 struct FusedShape {
-    // queues of 256 entries and more live in device memory (GlobalSelect)
-    static constexpr bool mem_queues = KR >= 4;
+    static constexpr bool mem_queues = queues_in_memory(KR);
     static constexpr int NC = 4;
     // thread-queue buffer: 64*T keys per query
     static constexpr int T = mem_queues ? 2 : SelParams<KR>::T;
+    // pool of thread-queue buffers behind each memory queue, in registers
+    // of 64 keys, and the keys of one (query, chunk) row of partial results
+    static constexpr int PR = mem_queues ? KR / 2 : 0;
+    static constexpr int ROW = 64 * (KR + PR);
     static constexpr bool wide = RB > 512;
     static constexpr int QPB = wide ? 1 : 2;
     static constexpr int DPB = wide ? 1 : 2;
@@ -356,11 +527,14 @@ struct FusedArgs {
     int32_t valid;        // leading elements per row that are real (rest zero)
     int64_t chunk_len;
     int32_t nchunks, nqb, keff;
-    uint64_t* part;       // [nq][nchunks][64 * KR] keys
-    uint32_t* bound;      // [nq] order-mapped score bound shared by the chunks of a query
+    uint64_t* part;       // [nq][nchunks][ROW] keys: each chunk's queue (and pool)
+    // scores shared by the chunks of a query: rank points [nq][nchunks][4]
+    // when queues live in memory, else one order-mapped bound per query
+    uint32_t* bound;
 };
 
-// Chunks of one query share a bound on its selection score: every
+// Chunks of one query with register queues share a bound on its selection
+// score: every
 // kBoundEvery steps a consumer tightens its queries' filters with the bound
 // published so far and publishes its own k-th score (a valid bound for every
 // chunk of the query: that chunk already holds keff candidates scoring at
@@ -424,6 +598,11 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
 
     __shared__ __align__(16) uint4 btile[NBUF][BN * GR];
     __shared__ __align__(16) float scores[2][BN * LDQ];
+    // per-row values of each tile the consumers need (||y||^2, 1/scale),
+    // staged by producer waves 0 (and 1) with the tile, so that consumers
+    // issue no global loads per step
+    constexpr int NY = (L2 ? 1 : 0) + (Op::SCALED ? 1 : 0);
+    __shared__ float ystage[NBUF][NY > 0 ? NY : 1][BN];
 
     const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)args.nqb * args.nchunks);
     const int64_t chunk = logical / args.nqb;
@@ -455,6 +634,16 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
     }
     auto load_tile = [&](int64_t t0, int buf) {
         const bool tail = t0 + BN > c1;  // wave-uniform
+        if (wave < NY) {
+            const float* ysrc = (L2 && wave == 0) ? args.yn : args.yinv;
+            const int64_t row = t0 + lane < c1 ? t0 + lane : c1 - 1;
+            if constexpr (VEC) {
+                __builtin_amdgcn_global_load_lds((gbl_ptr_t)(ysrc + row), (lds_ptr_t)&ystage[buf][wave][0],
+                                                 4, 0, 0);
+            } else {
+                ystage[buf][wave][lane] = ysrc[row];
+            }
+        }
 #pragma unroll
         for (int t = 0; t < LPW; ++t) {
             int64_t row = t0 + lrow[t];
@@ -489,7 +678,11 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
         if (nsteps > 0) load_tile(c0, 0);
         if (NBUF == 3 && nsteps > 1) {
             load_tile(c0 + BN, 1);
-            __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW>());  // tile 0 has landed
+            // tile 0 has landed (waves < NY load one more value per tile)
+            if (wave < NY)
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW + 1>());
+            else
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW>());
         } else {
             __builtin_amdgcn_s_waitcnt(0);
         }
@@ -553,7 +746,9 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
                 // next step's tile (and this step's score stores) must have
                 // landed; with three buffers the loads of the tile after it
                 // may stay in flight
-                if (NBUF == 3 && ahead < nsteps)
+                if (NBUF == 3 && ahead < nsteps && wave < NY)
+                    __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW + 1>());
+                else if (NBUF == 3 && ahead < nsteps)
                     __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW>());
                 else
                     __builtin_amdgcn_s_waitcnt(0);
@@ -566,14 +761,18 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
         // same for every candidate of a query and does not change its rank.
         // Scaled formats multiply q.y by the query's and the row's 1/scale.
         const int cw = wave - kProducers;
-        using Sel = typename std::conditional<S::mem_queues, GlobalSelect<KR, T, QW>,
+        using Sel = typename std::conditional<S::mem_queues, GlobalSelect<KR, T, QW, S::PR>,
                                               MultiSelect<KR, T, QW>>::type;
         Sel sel;
+        const int64_t qf = q0 + cw * QW;
         if constexpr (S::mem_queues) {
-            const int64_t qf = q0 + cw * QW;
             const int64_t left = args.nq - qf;
-            sel.init(args.keff, args.part + (qf * args.nchunks + chunk) * KS,
-                     (int64_t)args.nchunks * KS, (int)(left < 0 ? 0 : left < QW ? left : QW));
+            sel.init(args.keff, args.part + (qf * args.nchunks + chunk) * S::ROW,
+                     (int64_t)args.nchunks * S::ROW, (int)(left < 0 ? 0 : left < QW ? left : QW),
+                     args.bound && left > 0
+                         ? args.bound + (qf * args.nchunks + chunk) * kRankPoints
+                         : nullptr,
+                     args.nchunks);
         } else {
             sel.init(args.keff);
         }
@@ -585,20 +784,27 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
         }
         __syncthreads();
         float ynext = 0.f, ysnext = 1.f;
-        if (c0 + lane < c1) {
-            if (L2) ynext = args.yn[c0 + lane];
-            if (Op::SCALED) ysnext = args.yinv[c0 + lane];
+        if (nsteps > 0) {
+            if (L2) ynext = ystage[0][0][lane];
+            if (Op::SCALED) ysnext = ystage[0][L2 ? 1 : 0][lane];
         }
         for (int64_t s = 0; s <= nsteps; ++s) {
-            if ((s & (kBoundEvery - 1)) == 0 || s == nsteps) exchange_bounds(sel, args, q0 + cw * QW, lane);
+            if constexpr (S::mem_queues) {
+                // often early, while the queues fill, then every 64 steps
+                if (args.bound && (s == 4 || s == 8 || s == 16 || s == 32 || (s & 63) == 0))
+                    sel.exchange(args.bound, args.nchunks, qf, args.nq);
+            } else if ((s & (kBoundEvery - 1)) == 0 || s == nsteps) {
+                exchange_bounds(sel, args, qf, lane);
+            }
             if (s >= 1) {
                 const float* slot = scores[(s - 1) & 1];
                 const int64_t g = c0 + (s - 1) * BN + lane;
                 const bool ok = g < c1;
                 const float ynv = ynext, ysv = ysnext;
-                if (g + BN < c1) {
-                    if (L2) ynext = args.yn[g + BN];
-                    if (Op::SCALED) ysnext = args.yinv[g + BN];
+                // tile s sits in buffer s % NBUF until step s + 1 reloads it
+                if (s < nsteps) {
+                    if (L2) ynext = ystage[s % NBUF][0][lane];
+                    if (Op::SCALED) ysnext = ystage[s % NBUF][L2 ? 1 : 0][lane];
                 }
                 float score[QW];
                 const float* col = slot + lane * LDQ + cw * QW;
@@ -628,13 +834,13 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
             __syncthreads();
         }
         sel.finish();
-        exchange_bounds(sel, args, q0 + cw * QW, lane);
         if constexpr (!S::mem_queues) {
+            exchange_bounds(sel, args, qf, lane);
 #pragma unroll
             for (int qq = 0; qq < QW; ++qq) {
                 const int64_t q = q0 + cw * QW + qq;
                 if (q < args.nq) {
-                    uint64_t* out = args.part + (q * args.nchunks + chunk) * KS;
+                    uint64_t* out = args.part + (q * args.nchunks + chunk) * S::ROW;
 #pragma unroll
                     for (int r = 0; r < KR; ++r) out[r * 64 + lane] = sel.key(qq, r);
                 }
@@ -643,32 +849,41 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
     }
 }
 
-// bound[q] = order-mapped +inf (no bound yet).
-static __global__ void clear_bounds_kernel(uint32_t* __restrict__ bound, int64_t nq) {
+static __global__ void fill_bounds_kernel(uint32_t* __restrict__ bound, int64_t n, uint32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nq) bound[i] = 0xFF800000u;
+    if (i < n) bound[i] = v;
 }
 
-inline mk_status clear_bounds(uint32_t* bound, int64_t nq, hipStream_t s) {
-    hipLaunchKernelGGL(clear_bounds_kernel, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, s,
-                       bound, nq);
+// Words of the bound array of a search with nchunks chunks.
+inline int64_t bound_words(int KR, int64_t nq, int64_t nchunks) {
+    return queues_in_memory(KR) ? nq * nchunks * kRankPoints : nq;
+}
+
+// No bound yet: rank points "no rows proven" (kNoBound), per-query bounds
+// order-mapped +inf.
+inline mk_status clear_bounds(int KR, uint32_t* bound, int64_t nq, int64_t nchunks, hipStream_t s) {
+    const int64_t n = bound_words(KR, nq, nchunks);
+    if (n == 0) return MK_OK;
+    hipLaunchKernelGGL(fill_bounds_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, bound,
+                       n, queues_in_memory(KR) ? kNoBound : 0xFF800000u);
     MK_LAUNCHED();
     return MK_OK;
 }
 
-// Chunking of the database.  Every chunk a query's rows are split into costs
-// that query about keff insertions into its selector even with the shared
-// bound (and the first about keff (1 + ln(chunk / keff))), so long queues get
+// Chunking of the database.  Chunks of a query that run at the same time
+// each fill their queue before shared bounds can help, so long queues get
 // fewer, longer chunks: about 4 workgroups per CU for queues of 512+ entries,
-// 16 otherwise, chunks of at least 32 queue lengths, and among chunk counts
-// within 25% of that target the one whose last wave of workgroups is fullest.
+// 16 otherwise, chunks of at least 32 queue lengths, at most kMaxRankChunks
+// chunks when queues live in memory, and among chunk counts within 25% of
+// that target the one whose last wave of workgroups is fullest.
 inline void plan_chunks(int64_t nq, int64_t nb, int BQ, int BN, int KS, int64_t* nqb,
                         int64_t* nchunks, int64_t* chunk_len) {
     constexpr int64_t kCUs = 256;
     *nqb = ceil_div(nq, BQ);
     const int64_t target = (KS >= 512 ? 4 : 16) * kCUs;
     const int64_t want = ceil_div(target, *nqb);
-    const int64_t max_by_len = nb / (32 * KS) > 1 ? nb / (32 * KS) : 1;
+    int64_t max_by_len = nb / (32 * KS) > 1 ? nb / (32 * KS) : 1;
+    if (queues_in_memory(KS / 64) && max_by_len > kMaxRankChunks) max_by_len = kMaxRankChunks;
     int64_t hi = want < max_by_len ? want : max_by_len;
     if (hi < 1) hi = 1;
     int64_t lo = (hi * 3) / 4 > 1 ? (hi * 3) / 4 : 1;
@@ -693,7 +908,8 @@ constexpr int kMaxDim = 512;
 
 template <int KR>
 __global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
-    const uint64_t* __restrict__ part, int32_t nchunks, const float* __restrict__ xq, int64_t nq,
+    const uint64_t* __restrict__ part, int32_t nchunks, int32_t row, const float* __restrict__ xq,
+    int64_t nq,
     const float* __restrict__ xb, int32_t d, int32_t vec, int32_t l2, int32_t k, int32_t keff,
     float* __restrict__ D, int64_t* __restrict__ I) {
     constexpr int T = SelParams<KR>::T;
@@ -708,7 +924,7 @@ __global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
 
     WaveSelect<KR, T> ws;
     ws.init(keff);
-    const uint64_t* p = part + q * nchunks * KS;
+    const uint64_t* p = part + q * nchunks * row;
     // Each chunk's list is sorted; only its first keff entries can survive.
     const int per = (keff + 63) & ~63;
 #pragma unroll 1
@@ -716,7 +932,7 @@ __global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
 #pragma unroll 1
         for (int e = 0; e < per; e += 64) {
             const int i = e + lane;
-            if (ws.push(i < keff ? p[(int64_t)c * KS + i] : kSentinel)) ws.merge();
+            if (ws.push(i < keff ? p[(int64_t)c * row + i] : kSentinel)) ws.merge();
         }
     }
     ws.finish();

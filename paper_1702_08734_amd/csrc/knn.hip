@@ -64,10 +64,10 @@ mk_status knn_launch(const float* xq, int64_t nq, const float* xb, const float* 
     plan_chunks(nq, nb, S::BQ, S::BN, KS, &nqb, &nchunks, &chunk_len);
 
     Scratch part, bound;
-    mk_status st = part.alloc(sizeof(uint64_t) * (size_t)nq * (size_t)nchunks * KS, stream);
+    mk_status st = part.alloc(sizeof(uint64_t) * (size_t)nq * (size_t)nchunks * S::ROW, stream);
     if (st != MK_OK) return st;
-    MK_TRY(bound.alloc(sizeof(uint32_t) * (size_t)nq, stream));
-    MK_TRY(clear_bounds(bound.as<uint32_t>(), nq, stream));
+    MK_TRY(bound.alloc(sizeof(uint32_t) * (size_t)bound_words(KR, nq, nchunks), stream));
+    MK_TRY(clear_bounds(KR, bound.as<uint32_t>(), nq, nchunks, stream));
     const int64_t nblocks = nqb * nchunks;
     MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
     FusedArgs a{xq, xb, yn, nullptr, nullptr, nq, nb, d, d, chunk_len, (int32_t)nchunks,
@@ -83,8 +83,8 @@ mk_status knn_launch(const float* xq, int64_t nq, const float* xb, const float* 
         ProfScope prof("knn_merge_rerank", stream);
         hipLaunchKernelGGL((knn_merge_rerank<KR>), dim3((unsigned)ceil_div(nq, kMergeWaves)),
                            dim3(64 * kMergeWaves), 0, stream, part.as<uint64_t>(),
-                           (int32_t)nchunks, xq, nq, xb, d, (int32_t)vec, (int32_t)l2, k, keff, D,
-                           I);
+                           (int32_t)nchunks, (int32_t)S::ROW, xq, nq, xb, d, (int32_t)vec,
+                           (int32_t)l2, k, keff, D, I);
         MK_LAUNCHED();
     }
     return MK_OK;
@@ -141,7 +141,7 @@ mk_status rerank_launch(const uint64_t* keys, int64_t nq, int32_t R, const float
                         int64_t* I, hipStream_t s) {
     ProfScope prof("rerank", s);
     hipLaunchKernelGGL((knn_merge_rerank<KR>), dim3((unsigned)ceil_div(nq, kMergeWaves)),
-                       dim3(64 * kMergeWaves), 0, s, keys, 1, xq, nq, xb, d, (int32_t)vec,
+                       dim3(64 * kMergeWaves), 0, s, keys, 1, 64 * KR, xq, nq, xb, d, (int32_t)vec,
                        (int32_t)l2, k, R, D, I);
     MK_LAUNCHED();
     return MK_OK;

@@ -85,10 +85,10 @@ mk_status lowp_launch(const float* xq, const void* xq_lp, const float* xq_inv, i
     int64_t nqb, nchunks, chunk_len;
     plan_chunks(nq, nb, S::BQ, S::BN, KS, &nqb, &nchunks, &chunk_len);
     Scratch part, bound;
-    mk_status st = part.alloc(sizeof(uint64_t) * (size_t)nq * (size_t)nchunks * KS, stream);
+    mk_status st = part.alloc(sizeof(uint64_t) * (size_t)nq * (size_t)nchunks * S::ROW, stream);
     if (st != MK_OK) return st;
-    MK_TRY(bound.alloc(sizeof(uint32_t) * (size_t)nq, stream));
-    MK_TRY(clear_bounds(bound.as<uint32_t>(), nq, stream));
+    MK_TRY(bound.alloc(sizeof(uint32_t) * (size_t)bound_words(KR, nq, nchunks), stream));
+    MK_TRY(clear_bounds(KR, bound.as<uint32_t>(), nq, nchunks, stream));
     const int64_t nblocks = nqb * nchunks;
     MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
     const int32_t ld = lowp_stride(d);
@@ -107,7 +107,8 @@ mk_status lowp_launch(const float* xq, const void* xq_lp, const float* xq_inv, i
         ProfScope prof("knn_merge_rerank", stream);
         hipLaunchKernelGGL((knn_merge_rerank<KR>), dim3((unsigned)ceil_div(nq, kMergeWaves)),
                            dim3(64 * kMergeWaves), 0, stream, part.as<uint64_t>(),
-                           (int32_t)nchunks, xq, nq, xb, d, (int32_t)vec, (int32_t)l2, k, R, D, I);
+                           (int32_t)nchunks, (int32_t)S::ROW, xq, nq, xb, d, (int32_t)vec,
+                           (int32_t)l2, k, R, D, I);
         MK_LAUNCHED();
     }
     return MK_OK;

@@ -126,6 +126,40 @@ def test_knn_integer_ties(api):
         np.testing.assert_array_equal(D.cpu().numpy().astype(np.float64), Do)
 
 
+@pytest.mark.parametrize("k", [200, 300, 1024])
+def test_knn_many_chunks_integer_ties(api, k):
+    # 150,000 small-integer rows: many database chunks share score bounds
+    # while exact ties abound (distances are exact in FP32); the result must
+    # equal the oracle's exactly, lower index first among equal distances
+    say(f"knn many chunks, integer ties, k={k}")
+    rng = np.random.default_rng(11 + k)
+    xb = rng.integers(-2, 3, size=(150_000, 16)).astype(np.float32)
+    xq = rng.integers(-2, 3, size=(100, 16)).astype(np.float32)
+    D, I = api.knn_search(dev(xq), dev(xb), k)
+    torch.cuda.synchronize()
+    Do, Io = oracle.knn(xq, xb, k, oracle.METRIC_L2)
+    np.testing.assert_array_equal(I.cpu().numpy(), Io)
+    np.testing.assert_array_equal(D.cpu().numpy().astype(np.float64), Do)
+
+
+@pytest.mark.parametrize("k", [100, 256, 1024])
+def test_knn_best_rows_in_last_chunk(api, k):
+    # rows ordered from far to near for query 0, so its whole answer sits in
+    # the last chunk and every earlier chunk publishes loose points
+    say(f"knn best rows last, k={k}")
+    rng = np.random.default_rng(29 + k)
+    xb = rng.standard_normal((200_000, 32)).astype(np.float32)
+    xq = rng.standard_normal((64, 32)).astype(np.float32)
+    d0 = ((xb.astype(np.float64) - xq[0]) ** 2).sum(1)
+    xb = np.ascontiguousarray(xb[np.argsort(-d0, kind="stable")])
+    D, I = api.knn_search(dev(xq), dev(xb), k)
+    torch.cuda.synchronize()
+    rows = np.array([0, 1, 31, 63])
+    fails = check_rows(D.cpu().numpy()[rows], I.cpu().numpy()[rows], xq, xb, rows, k)
+    assert not fails, fails[:10]
+    assert I[0].min().item() >= 200_000 - 4 * k
+
+
 def test_knn_empty_query_batch(api):
     xb = dev(np.ones((10, 8), np.float32))
     D, I = api.knn_search(dev(np.zeros((0, 8), np.float32)), xb, 3)
