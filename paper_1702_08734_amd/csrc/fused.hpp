@@ -141,76 +141,115 @@ constexpr int kRankPoints = 4;
 constexpr int kMaxRankChunks = 16;  // chunks per query when queues live in memory
 constexpr uint32_t kNoBound = 0xFFFFFFFFu;
 
-// QW selectors whose wave queues (64*KR keys per query, lane-stride) live in
-// device memory -- the kernel's own partial-result rows -- instead of
-// registers: only the dense thread-queue buffers and the per-query
-// thresholds stay in registers, so one consumer can serve as many queries for
-// 256- and 1024-entry queues as for short ones.  A full buffer is not merged
-// at once: it is stored as one run of a pool of PR/T runs behind the queue,
-// and only a full pool is merged (sorted, PR registers, and merged into the
-// queue keeping the keff smallest), so the cost of the 64*KR-wide merge
-// network is shared by up to 64*PR candidates instead of 64*T.  The
-// admission threshold is then refreshed less often; it stays a valid filter
-// (the queue's keff-th key only decreases).  Each lane only ever reads back
-// what it wrote itself.  A merge publishes the queue's rank points (above).
-// Queries at or beyond nvalid never take candidates and are never written.
-template <int KR, int T, int QW, int PR>
-struct GlobalSelect {
+// s_waitcnt immediate (gfx9 encoding) that waits for all LDS operations.
+constexpr int waitcnt_lgkm0() { return 0xF | (0x7 << 4) | (0x0 << 8) | (0x3 << 14); }
+
+// Wave-wide reductions and scans over all 64 lanes.
+__device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
+    v = umin64(v, xor_lane64<1>(v));
+    v = umin64(v, xor_lane64<2>(v));
+    v = umin64(v, xor_lane64<4>(v));
+    v = umin64(v, xor_lane64<8>(v));
+    v = umin64(v, xor_lane64<16>(v));
+    return umin64(v, xor_lane64<32>(v));
+}
+__device__ __forceinline__ uint64_t wave_max64(uint64_t v) {
+    v = umax64(v, xor_lane64<1>(v));
+    v = umax64(v, xor_lane64<2>(v));
+    v = umax64(v, xor_lane64<4>(v));
+    v = umax64(v, xor_lane64<8>(v));
+    v = umax64(v, xor_lane64<16>(v));
+    return umax64(v, xor_lane64<32>(v));
+}
+__device__ __forceinline__ int wave_inclusive_sum(int v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o);
+        v += lane >= o ? u : 0;
+    }
+    return v;
+}
+
+// QW selectors for queues of 256 entries and more, whose candidates live in
+// device memory -- the kernel's own partial-result rows.  A candidate that
+// beats its query's threshold is appended to the query's pool (one store per
+// wave, positions from the ballot); nothing is kept sorted while the chunk
+// is scanned.  When a pool nears its capacity (twice the queue) it is cut
+// back to about keff keys by a radix selection over the 64-bit keys: a
+// histogram of NB bins over [smallest, largest] key, built with LDS atomics,
+// locates the bin holding the keff-th smallest key, and the search recurses
+// into that bin until at most `target` keys remain at or below its upper
+// edge.  The kept keys are the smallest ones (bins are monotone in the key),
+// at least keff of them, and the largest kept key + 1 becomes the threshold:
+// a key above it cannot be among the keff smallest.  A selection costs a few
+// passes over 2*64*KR keys for about 64*KR insertions, where a sorted queue
+// pays a full merge network every 64-128.  At the end the pool is cut to at
+// most 64*KR keys and padded with sentinels; the second pass selects from
+// it.  The level-0 histogram also yields the rank points published for the
+// other chunks (see above).  Queries at or beyond nvalid never take
+// candidates and are never written.
+template <int KR, int QW, int NB>
+struct PoolSelect {
     static constexpr int kQueries = QW;
-    static constexpr int kRuns = PR / T;  // buffers per pool
-    static_assert(PR % T == 0 && PR <= KR, "pool of whole buffers, at most a queue long");
+    static constexpr int KS = 64 * KR;
+    static constexpr int CAP = 2 * KS;  // pool capacity in keys
+    static constexpr int PRG = CAP / 64;
+    static constexpr int NBL = NB / 64;  // bins per lane in a scan
+    static constexpr int LOGNB = NB == 1024 ? 10 : NB == 512 ? 9 : NB == 256 ? 8 : 7;
+    static_assert(NB == 1024 || NB == 512 || NB == 256 || NB == 128, "bins");
     typedef uint32_t vq __attribute__((ext_vector_type(QW)));
     typedef float vqf __attribute__((ext_vector_type(QW)));
-    vq tl[T], th[T];     // thread-queue buffers
     vq kl, kh;           // admission threshold key of each query (wave-uniform)
     vqf kf;              // its score
     vq bdu;              // order-mapped score bound from the chunks' rank points
-    int cnt[QW];         // keys in each query's buffer
-    int runs[QW];        // buffers stored in each query's pool
-    uint32_t stored;     // bit q: query q's queue in memory holds merged keys
-    uint64_t* wbase;     // queue of query q at wbase + q * wstride, its pool right after
+    int cnt[QW];         // keys in each query's pool
+    uint64_t* wbase;     // pool of query q at wbase + q * wstride
     int64_t wstride;
     uint32_t* rpub;      // rank points of query q, this chunk, at rpub + q * rstride
     int64_t rstride;
+    uint32_t* hist;      // NB zeroed counters in LDS, private to this wave
     int rank[kRankPoints];
     int keff, nvalid;
 
     __device__ __forceinline__ void init(int k_eff, uint64_t* base, int64_t stride, int valid,
-                                         uint32_t* rank_base, int nchunks) {
+                                         uint32_t* rank_base, int nchunks, uint32_t* bins) {
         keff = k_eff;
         wbase = base;
         wstride = stride;
         nvalid = valid;
         rpub = rank_base;
         rstride = (int64_t)nchunks * kRankPoints;
+        hist = bins;
         const int r0 = (k_eff + nchunks - 1) / nchunks;
         rank[0] = r0;
         rank[1] = 2 * r0 < k_eff ? 2 * r0 : k_eff;
         rank[2] = 4 * r0 < k_eff ? 4 * r0 : k_eff;
         rank[3] = k_eff;
-#pragma unroll
-        for (int i = 0; i < T; ++i) tl[i] = th[i] = ~0u;
         kl = kh = ~0u;
         kf = INFINITY;
         bdu = kNoBound;
 #pragma unroll
         for (int q = 0; q < QW; ++q) {
             cnt[q] = 0;
-            runs[q] = 0;
             if (q >= valid) {  // never admits a candidate
                 kf[q] = -INFINITY;
                 kl[q] = kh[q] = 0u;
             }
         }
-        stored = 0;
+        const int lane = lane_id();
+#pragma unroll
+        for (int j = 0; j < NBL; ++j) hist[lane * NBL + j] = 0u;
     }
 
-    // Lower query q's admission threshold to its queue's k-th key kk or the
-    // bound, whichever is smaller; a candidate scoring exactly the bound
-    // still competes (its key is below the bound's key for any index).
+    // Lower query q's admission threshold to kk or the bound, whichever is
+    // smaller; a candidate scoring exactly the bound still competes (its key
+    // is below the bound's key for any index).
     __device__ __forceinline__ void set_threshold(int q, uint64_t kk) {
         const uint64_t bk = ((uint64_t)bdu[q] << 32) | 0xFFFFFFFFull;
-        const uint64_t th_key = kk < bk ? kk : bk;
+        const uint64_t cur = ((uint64_t)kh[q] << 32) | kl[q];
+        uint64_t th_key = kk < bk ? kk : bk;
+        th_key = th_key < cur ? th_key : cur;
         kl[q] = (uint32_t)th_key;
         kh[q] = (uint32_t)(th_key >> 32);
         const uint32_t hi = (uint32_t)(th_key >> 32);
@@ -224,73 +263,142 @@ struct GlobalSelect {
         }
     }
 
-    // Merge the first nruns buffers of query q's pool into its queue.
-    __device__ __forceinline__ void merge_pool(int q, int nruns) {
-        const int lane = lane_id();
-        uint64_t* wp = wbase + (int64_t)q * wstride;
-        const uint64_t* pp = wp + 64 * KR;
-        const bool have = (stored >> q) & 1u;
-        uint64_t ww[KR], pv[PR];
+    // Position of the t-th smallest key (1-based) in the histogram whose
+    // lane-local bins are h and lane-exclusive prefix excl (wave totals
+    // incl): its bin, and the keys in the bins before it and up to it.
+    // False when the histogram holds fewer than t keys.
+    __device__ __forceinline__ bool locate(const uint32_t (&h)[NBL], int excl, int incl, int t,
+                                           int& bin, int& before, int& upto) const {
+        int jl = NBL - 1, cb = incl, ci = incl, c = excl;
+        bool f = false;
 #pragma unroll
-        for (int r = 0; r < KR; ++r) ww[r] = have ? wp[r * 64 + lane] : kSentinel;
-#pragma unroll
-        for (int r = 0; r < PR; ++r) pv[r] = r / T < nruns ? pp[r * 64 + lane] : kSentinel;
-        ws_merge<KR, PR>(ww, pv);
-        const uint64_t kk = ws_element<KR>(ww, keff - 1);
-#pragma unroll
-        for (int r = 0; r < KR; ++r) wp[r * 64 + lane] = ww[r];
-        stored |= 1u << q;
-        if (rpub) {
-            // the queue is sorted: its entry at rank r scores at most the
-            // published value, as do the r - 1 before it
-            const uint32_t p0 = (uint32_t)(ws_element<KR>(ww, rank[0] - 1) >> 32);
-            const uint32_t p1 = (uint32_t)(ws_element<KR>(ww, rank[1] - 1) >> 32);
-            const uint32_t p2 = (uint32_t)(ws_element<KR>(ww, rank[2] - 1) >> 32);
-            const uint32_t p3 = (uint32_t)(kk >> 32);
-            if (lane == 0) {
-                uint64_t* rp = reinterpret_cast<uint64_t*>(rpub + (int64_t)q * rstride);
-                __hip_atomic_store(rp, ((uint64_t)p1 << 32) | p0, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(rp + 1, ((uint64_t)p3 << 32) | p2, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        for (int j = 0; j < NBL; ++j) {
+            const int c2 = c + (int)h[j];
+            if (!f && c2 >= t) {
+                jl = j;
+                cb = c;
+                ci = c2;
+                f = true;
             }
+            c = c2;
         }
-#pragma unroll
-        for (int qq = 0; qq < QW; ++qq) runs[qq] = qq == q ? 0 : runs[qq];
-        set_threshold(q, kk);
+        const uint64_t m = __ballot(excl < t && t <= incl);
+        if (!m) return false;
+        const int L = __builtin_ctzll(m);
+        bin = L * NBL + __builtin_amdgcn_readlane(jl, L);
+        before = __builtin_amdgcn_readlane(cb, L);
+        upto = __builtin_amdgcn_readlane(ci, L);
+        return true;
     }
 
-    // Store query q's buffer as the next run of its pool and empty it; merge
-    // the pool once it is full (or when `last`).
-    __device__ __forceinline__ void flush(int q, bool last) {
+    // Cut query q's pool to the keys at or below a bin edge such that at
+    // least keff and at most `target` keys remain (all of them when it
+    // holds no more than target), refresh its threshold and publish its
+    // rank points.
+    __device__ __forceinline__ void refine(int q, int target) {
         const int lane = lane_id();
-        int r = 0;
+        uint64_t* pp = wbase + (int64_t)q * wstride;
+        int n = 0;
 #pragma unroll
-        for (int qq = 0; qq < QW; ++qq) r = qq == q ? runs[qq] : r;
-        int c = 0;
-#pragma unroll
-        for (int qq = 0; qq < QW; ++qq) c = qq == q ? cnt[qq] : c;
-        if (c > 0) {
-            uint64_t* pp = wbase + (int64_t)q * wstride + 64 * KR + (int64_t)r * 64 * T;
-#pragma unroll
-            for (int i = 0; i < T; ++i) pp[i * 64 + lane] = ((uint64_t)th[i][q] << 32) | tl[i][q];
-#pragma unroll
-            for (int i = 0; i < T; ++i) {
-                tl[i][q] = ~0u;
-                th[i][q] = ~0u;
-            }
-            r += 1;
-#pragma unroll
-            for (int qq = 0; qq < QW; ++qq) {
-                cnt[qq] = qq == q ? 0 : cnt[qq];
-                runs[qq] = qq == q ? r : runs[qq];
+        for (int qq = 0; qq < QW; ++qq) n = qq == q ? cnt[qq] : n;
+        if (n <= target) return;
+        // the appends of every lane of this wave are visible to its loads
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        uint64_t lo = kSentinel, hi = 0;
+#pragma unroll 4
+        for (int r = 0; r < PRG; ++r) {
+            const int i = r * 64 + lane;
+            if (i < n) {
+                const uint64_t k = pp[i];
+                lo = umin64(lo, k);
+                hi = umax64(hi, k);
             }
         }
-        if (r == kRuns || last) merge_pool(q, r);
+        lo = wave_min64(lo);
+        hi = wave_max64(hi);
+        uint32_t pts[3] = {kNoBound, kNoBound, kNoBound};
+        uint64_t cut = hi;
+        int below = 0;
+#pragma unroll 1
+        for (int level = 0; level < 10; ++level) {
+            const uint64_t range = hi - lo;
+            const int bits = range ? 64 - __builtin_clzll(range) : 0;
+            const int shift = bits > LOGNB ? bits - LOGNB : 0;
+#pragma unroll 4
+            for (int r = 0; r < PRG; ++r) {
+                const int i = r * 64 + lane;
+                if (i < n) {
+                    const uint64_t k = pp[i];
+                    if (k >= lo && k <= hi) atomicAdd(&hist[(uint32_t)((k - lo) >> shift)], 1u);
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(waitcnt_lgkm0());
+            uint32_t h[NBL];
+            int tot = 0;
+#pragma unroll
+            for (int j = 0; j < NBL; ++j) {
+                h[j] = hist[lane * NBL + j];
+                tot += (int)h[j];
+            }
+#pragma unroll
+            for (int j = 0; j < NBL; ++j) hist[lane * NBL + j] = 0u;
+            const int incl = wave_inclusive_sum(tot);
+            const int excl = incl - tot;
+            // upper edge key of bin b, clamped to hi
+            auto edge = [&](int b) -> uint64_t {
+                const uint64_t off = ((uint64_t)(b + 1) << shift) - 1;
+                return off >= range ? hi : lo + off;
+            };
+            if (level == 0) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    int b, bf, up;
+                    if (locate(h, excl, incl, rank[j], b, bf, up)) pts[j] = (uint32_t)(edge(b) >> 32);
+                }
+            }
+            int b, bf, up;
+            if (!locate(h, excl, incl, keff - below, b, bf, up)) break;  // cannot happen: n > keff
+            if (below + up <= target || shift == 0) {
+                cut = edge(b);
+                break;
+            }
+            below += bf;
+            const uint64_t nhi = edge(b);
+            lo = lo + ((uint64_t)b << shift);
+            hi = nhi;
+        }
+        // keep the keys at or below the cut, packed at the front
+        int kept = 0;
+        uint64_t top = 0;
+#pragma unroll 4
+        for (int r = 0; r < PRG; ++r) {
+            const int i = r * 64 + lane;
+            const uint64_t k = i < n ? pp[i] : kSentinel;
+            const bool keep = k <= cut;
+            const uint64_t bal = __ballot(keep);
+            const int pos = kept + (int)__builtin_amdgcn_mbcnt_hi(
+                                        (uint32_t)(bal >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            if (keep) pp[pos] = k;
+            top = keep ? umax64(top, k) : top;
+            kept += __popcll(bal);
+        }
+        top = wave_max64(top);
+#pragma unroll
+        for (int qq = 0; qq < QW; ++qq) cnt[qq] = qq == q ? kept : cnt[qq];
+        set_threshold(q, top + 1);
+        if (rpub && lane == 0) {
+            uint64_t* rp = reinterpret_cast<uint64_t*>(rpub + (int64_t)q * rstride);
+            __hip_atomic_store(rp, ((uint64_t)pts[1] << 32) | pts[0], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(rp + 1, ((uint64_t)(uint32_t)(top >> 32) << 32) | pts[2],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 
     __device__ __forceinline__ void offer(const float (&score)[QW], uint32_t idx, bool ok) {
         uint32_t full = 0;
+        const int lane = lane_id();
 #pragma unroll
         for (int q = 0; q < QW; ++q) {
             if (__any(ok && score[q] <= kf[q])) {
@@ -299,31 +407,39 @@ struct GlobalSelect {
                 const bool take = key < kth;
                 const uint64_t bal = __ballot(take);
                 if (bal) {
-                    uint64_t tq[T];
-#pragma unroll
-                    for (int i = 0; i < T; ++i) tq[i] = ((uint64_t)th[i][q] << 32) | tl[i][q];
-                    cnt[q] = tq_append<T>(tq, key, take, bal, cnt[q]);
-#pragma unroll
-                    for (int i = 0; i < T; ++i) {
-                        tl[i][q] = (uint32_t)tq[i];
-                        th[i][q] = (uint32_t)(tq[i] >> 32);
-                    }
-                    if (cnt[q] > 64 * (T - 1)) full |= 1u << q;
+                    const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                    if (take && cnt[q] + below < CAP) wbase[(int64_t)q * wstride + cnt[q] + below] = key;
+                    cnt[q] += __popcll(bal);
+                    if (cnt[q] > CAP - 64) full |= 1u << q;
                 }
             }
         }
+        (void)lane;
         while (full) {
             const int q = __builtin_ctz(full);
             full &= full - 1;
-            flush(q, false);
+            refine(q, (keff + CAP) / 2);
         }
     }
 
-    // Final merge of every valid query (also writes the all-sentinel queue
-    // of a query that never took a candidate).
+    // Cut every valid query's pool to at most 64*KR keys and pad it with
+    // sentinels to that length: the chunk's unsorted candidate list.
     __device__ __forceinline__ void finish() {
+        const int lane = lane_id();
 #pragma unroll 1
-        for (int q = 0; q < nvalid; ++q) flush(q, true);
+        for (int q = 0; q < nvalid; ++q) {
+            refine(q, KS);
+            int n = 0;
+#pragma unroll
+            for (int qq = 0; qq < QW; ++qq) n = qq == q ? cnt[qq] : n;
+            uint64_t* pp = wbase + (int64_t)q * wstride;
+#pragma unroll
+            for (int r = 0; r < KR; ++r) {
+                const int i = r * 64 + lane;
+                if (i >= n) pp[i] = kSentinel;
+            }
+        }
     }
 
     // Tighten every query's bound from the rank points all chunks have
@@ -499,11 +615,10 @@ struct FusedShape {
     static constexpr bool mem_queues = queues_in_memory(KR);
     static constexpr int NC = 4;
     // thread-queue buffer: 64*T keys per query
-    static constexpr int T = mem_queues ? 2 : SelParams<KR>::T;
-    // pool of thread-queue buffers behind each memory queue, in registers
-    // of 64 keys, and the keys of one (query, chunk) row of partial results
-    static constexpr int PR = mem_queues ? KR / 2 : 0;
-    static constexpr int ROW = 64 * (KR + PR);
+    static constexpr int T = SelParams<KR>::T;
+    // keys of one (query, chunk) row of partial results: a sorted queue, or
+    // a candidate pool of twice the queue length
+    static constexpr int ROW = (mem_queues ? 2 : 1) * 64 * KR;
     static constexpr bool wide = RB > 512;
     static constexpr int QPB = wide ? 1 : 2;
     static constexpr int DPB = wide ? 1 : 2;
@@ -603,6 +718,17 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
     // issue no global loads per step
     constexpr int NY = (L2 ? 1 : 0) + (Op::SCALED ? 1 : 0);
     __shared__ float ystage[NBUF][NY > 0 ? NY : 1][BN];
+    // histogram bins of each consumer's pool selections: as many as the LDS
+    // left over allows (at most 1024)
+    constexpr int kLdsBytes = 160 * 1024;
+    constexpr int USED = NBUF * BN * GR * 16 + 2 * BN * LDQ * 4 + NBUF * (NY > 0 ? NY : 1) * BN * 4;
+    constexpr int NBINS = !S::mem_queues                             ? 1
+                          : USED + S::NC * 1024 * 4 <= kLdsBytes     ? 1024
+                          : USED + S::NC * 512 * 4 <= kLdsBytes      ? 512
+                          : USED + S::NC * 256 * 4 <= kLdsBytes      ? 256
+                                                                     : 128;
+    static_assert(!S::mem_queues || USED + S::NC * NBINS * 4 <= kLdsBytes, "LDS");
+    __shared__ uint32_t bins[S::mem_queues ? S::NC : 1][NBINS];
 
     const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)args.nqb * args.nchunks);
     const int64_t chunk = logical / args.nqb;
@@ -761,7 +887,7 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
         // same for every candidate of a query and does not change its rank.
         // Scaled formats multiply q.y by the query's and the row's 1/scale.
         const int cw = wave - kProducers;
-        using Sel = typename std::conditional<S::mem_queues, GlobalSelect<KR, T, QW, S::PR>,
+        using Sel = typename std::conditional<S::mem_queues, PoolSelect<KR, QW, NBINS>,
                                               MultiSelect<KR, T, QW>>::type;
         Sel sel;
         const int64_t qf = q0 + cw * QW;
@@ -772,7 +898,7 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
                      args.bound && left > 0
                          ? args.bound + (qf * args.nchunks + chunk) * kRankPoints
                          : nullptr,
-                     args.nchunks);
+                     args.nchunks, bins[S::mem_queues ? cw : 0]);
         } else {
             sel.init(args.keff);
         }
@@ -908,8 +1034,8 @@ constexpr int kMaxDim = 512;
 
 template <int KR>
 __global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
-    const uint64_t* __restrict__ part, int32_t nchunks, int32_t row, const float* __restrict__ xq,
-    int64_t nq,
+    const uint64_t* __restrict__ part, int32_t nchunks, int32_t row, int32_t nread,
+    const float* __restrict__ xq, int64_t nq,
     const float* __restrict__ xb, int32_t d, int32_t vec, int32_t l2, int32_t k, int32_t keff,
     float* __restrict__ D, int64_t* __restrict__ I) {
     constexpr int T = SelParams<KR>::T;
@@ -925,14 +1051,15 @@ __global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
     WaveSelect<KR, T> ws;
     ws.init(keff);
     const uint64_t* p = part + q * nchunks * row;
-    // Each chunk's list is sorted; only its first keff entries can survive.
-    const int per = (keff + 63) & ~63;
+    // The first nread entries of each chunk's row hold its candidates (a
+    // sorted list needs only its first keff).
+    const int per = (nread + 63) & ~63;
 #pragma unroll 1
     for (int c = 0; c < nchunks; ++c) {
 #pragma unroll 1
         for (int e = 0; e < per; e += 64) {
             const int i = e + lane;
-            if (ws.push(i < keff ? p[(int64_t)c * row + i] : kSentinel)) ws.merge();
+            if (ws.push(i < nread ? p[(int64_t)c * row + i] : kSentinel)) ws.merge();
         }
     }
     ws.finish();

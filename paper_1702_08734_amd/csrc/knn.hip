@@ -83,8 +83,8 @@ mk_status knn_launch(const float* xq, int64_t nq, const float* xb, const float* 
         ProfScope prof("knn_merge_rerank", stream);
         hipLaunchKernelGGL((knn_merge_rerank<KR>), dim3((unsigned)ceil_div(nq, kMergeWaves)),
                            dim3(64 * kMergeWaves), 0, stream, part.as<uint64_t>(),
-                           (int32_t)nchunks, (int32_t)S::ROW, xq, nq, xb, d, (int32_t)vec,
-                           (int32_t)l2, k, keff, D, I);
+                           (int32_t)nchunks, (int32_t)S::ROW, S::mem_queues ? KS : keff, xq, nq,
+                           xb, d, (int32_t)vec, (int32_t)l2, k, keff, D, I);
         MK_LAUNCHED();
     }
     return MK_OK;
@@ -141,7 +141,7 @@ mk_status rerank_launch(const uint64_t* keys, int64_t nq, int32_t R, const float
                         int64_t* I, hipStream_t s) {
     ProfScope prof("rerank", s);
     hipLaunchKernelGGL((knn_merge_rerank<KR>), dim3((unsigned)ceil_div(nq, kMergeWaves)),
-                       dim3(64 * kMergeWaves), 0, s, keys, 1, 64 * KR, xq, nq, xb, d, (int32_t)vec,
+                       dim3(64 * kMergeWaves), 0, s, keys, 1, 64 * KR, R, xq, nq, xb, d, (int32_t)vec,
                        (int32_t)l2, k, R, D, I);
     MK_LAUNCHED();
     return MK_OK;

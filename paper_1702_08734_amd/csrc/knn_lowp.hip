@@ -107,8 +107,8 @@ mk_status lowp_launch(const float* xq, const void* xq_lp, const float* xq_inv, i
         ProfScope prof("knn_merge_rerank", stream);
         hipLaunchKernelGGL((knn_merge_rerank<KR>), dim3((unsigned)ceil_div(nq, kMergeWaves)),
                            dim3(64 * kMergeWaves), 0, stream, part.as<uint64_t>(),
-                           (int32_t)nchunks, (int32_t)S::ROW, xq, nq, xb, d, (int32_t)vec,
-                           (int32_t)l2, k, R, D, I);
+                           (int32_t)nchunks, (int32_t)S::ROW, S::mem_queues ? KS : R, xq, nq, xb,
+                           d, (int32_t)vec, (int32_t)l2, k, R, D, I);
         MK_LAUNCHED();
     }
     return MK_OK;
