@@ -305,7 +305,7 @@ struct PoolSelect {
         // the appends of every lane of this wave are visible to its loads
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
         uint64_t lo = kSentinel, hi = 0;
-#pragma unroll 4
+#pragma unroll 8
         for (int r = 0; r < PRG; ++r) {
             const int i = r * 64 + lane;
             if (i < n) {
@@ -324,7 +324,7 @@ struct PoolSelect {
             const uint64_t range = hi - lo;
             const int bits = range ? 64 - __builtin_clzll(range) : 0;
             const int shift = bits > LOGNB ? bits - LOGNB : 0;
-#pragma unroll 4
+#pragma unroll 8
             for (int r = 0; r < PRG; ++r) {
                 const int i = r * 64 + lane;
                 if (i < n) {
@@ -370,7 +370,7 @@ struct PoolSelect {
         // keep the keys at or below the cut, packed at the front
         int kept = 0;
         uint64_t top = 0;
-#pragma unroll 4
+#pragma unroll 8
         for (int r = 0; r < PRG; ++r) {
             const int i = r * 64 + lane;
             const uint64_t k = i < n ? pp[i] : kSentinel;
@@ -411,15 +411,37 @@ struct PoolSelect {
                         (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
                     if (take && cnt[q] + below < CAP) wbase[(int64_t)q * wstride + cnt[q] + below] = key;
                     cnt[q] += __popcll(bal);
-                    if (cnt[q] > CAP - 64) full |= 1u << q;
                 }
             }
         }
         (void)lane;
-        while (full) {
-            const int q = __builtin_ctz(full);
-            full &= full - 1;
-            refine(q, (keff + CAP) / 2);
+        (void)full;
+    }
+
+    // Long selections (pools of 2048 keys) are batched across the consumers
+    // of a workgroup: one wave's selection stalls every wave at the next
+    // barrier, so when any consumer has a pool within three offers of its
+    // capacity (`urgent`), all of them cut every pool that is at least half
+    // way from keff to capacity in the same step.  A pool that could
+    // overflow in the next offer is cut anyway.
+    static constexpr bool kBatch = CAP >= 2048;
+    static constexpr int kUrgent = CAP - 192;
+    __device__ __forceinline__ bool urgent() const {
+        if (!kBatch) return false;
+        bool u = false;
+#pragma unroll
+        for (int q = 0; q < QW; ++q) u |= cnt[q] > kUrgent;
+        return u;
+    }
+    __device__ __forceinline__ void refine_pools(bool batch) {
+        const int level = batch ? (keff + CAP) / 2 : CAP - 64;
+        uint32_t m = 0;
+#pragma unroll
+        for (int q = 0; q < QW; ++q) m |= (cnt[q] > level ? 1u : 0u) << q;
+        while (m) {
+            const int q = __builtin_ctz(m);
+            m &= m - 1;
+            refine(q, keff + 128);
         }
     }
 
@@ -729,6 +751,7 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
                                                                      : 128;
     static_assert(!S::mem_queues || USED + S::NC * NBINS * 4 <= kLdsBytes, "LDS");
     __shared__ uint32_t bins[S::mem_queues ? S::NC : 1][NBINS];
+    __shared__ uint32_t urgent_flags[2][S::NC];
 
     const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)args.nqb * args.nchunks);
     const int64_t chunk = logical / args.nqb;
@@ -923,6 +946,15 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
                 exchange_bounds(sel, args, qf, lane);
             }
             if (s >= 1) {
+                if constexpr (S::mem_queues) {
+                    // consumers' urgency flags of the previous step
+                    bool batch = false;
+                    if (s >= 2) {
+#pragma unroll
+                        for (int c = 0; c < S::NC; ++c) batch |= urgent_flags[s & 1][c] != 0u;
+                    }
+                    sel.refine_pools(batch);
+                }
                 const float* slot = scores[(s - 1) & 1];
                 const int64_t g = c0 + (s - 1) * BN + lane;
                 const bool ok = g < c1;
@@ -956,6 +988,10 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
                     score[qq] = L2 ? fmaf(-2.f, c, ynv) : -c;
                 }
                 sel.offer(score, (uint32_t)g, ok);
+                if constexpr (S::mem_queues) {
+                    const bool u = sel.urgent();
+                    if (lane == 0) urgent_flags[(s + 1) & 1][cw] = u ? 1u : 0u;
+                }
             }
             __syncthreads();
         }
