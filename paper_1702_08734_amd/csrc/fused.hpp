@@ -548,6 +548,7 @@ struct PoolSelect {
 // the same component order and the sum over components is exact-order
 // independent of it.
 struct OpF32 {   // v_mfma_f32_16x16x4f32, four per granule
+    static constexpr int CONSUMERS = 4;
     static constexpr int EPG = 4;
     static constexpr int BYTES = 4;
     static constexpr bool SCALED = false;
@@ -559,7 +560,11 @@ struct OpF32 {   // v_mfma_f32_16x16x4f32, four per granule
         return c;
     }
 };
+// The low-precision tiles take the matrix cores a fraction of the FP32 time,
+// so their workgroups run eight consumer waves to keep up (rows of up to 256
+// bytes, whose producers fit the smaller register budget).
 struct OpBF16 {  // v_mfma_f32_16x16x32_bf16, one per granule
+    static constexpr int CONSUMERS = 8;
     static constexpr int EPG = 8;
     static constexpr int BYTES = 2;
     static constexpr bool SCALED = false;
@@ -569,6 +574,7 @@ struct OpBF16 {  // v_mfma_f32_16x16x32_bf16, one per granule
     }
 };
 struct OpFP8 {   // v_mfma_f32_16x16x32_fp8_fp8 (OCP E4M3), two per granule
+    static constexpr int CONSUMERS = 8;
     static constexpr int EPG = 16;
     static constexpr int BYTES = 1;
     static constexpr bool SCALED = true;
@@ -622,20 +628,28 @@ constexpr int waitcnt_vm() {
 
 // Workgroup of the fused kernel: 4 producer waves (one per SIMD) compute the
 // q.y tile of BQ queries x BN = 64 database rows per step on the matrix
-// cores and write it to one of two LDS slots, while 4 consumer waves run the
-// selectors of the previous step's tile from the other slot -- MFMA and VALU
-// selection overlap, one barrier per step.  Each producer owns QPB query
-// blocks x DPB database blocks of 16 (a 4-producer grid of QG x DG), each
-// consumer QW = BQ/4 queries.  BQ = 64, or 16 for rows over 512 bytes (LDS).
+// cores and write it to one of two LDS slots, while NC consumer waves (4 for
+// FP32, 8 for the low-precision formats) run the selectors of the previous
+// step's tile from the other slot -- MFMA and VALU selection overlap, one
+// barrier per step.  Each producer owns QPB query blocks x DPB database
+// blocks of 16 (a 4-producer grid of QG x DG), each consumer QW = BQ/NC
+// queries.  BQ = 64, or 16 for rows over 512 bytes (LDS).
 constexpr int kProducers = 4;
 
 // Queues of 256 entries and more live in device memory (GlobalSelect).
 constexpr bool queues_in_memory(int KR) { return KR >= 4; }
 
-template <int KR, int RB>
+template <class Op, int DP>
+constexpr int fused_consumers() {
+    return DP * Op::BYTES <= 256 ? Op::CONSUMERS : 4;
+}
+
+template <int KR, int RB, int NCONS = 4>
 struct FusedShape {
     static constexpr bool mem_queues = queues_in_memory(KR);
-    static constexpr int NC = 4;
+    static constexpr int NC = NCONS;
+    // waves per SIMD: the producers and consumers of one workgroup
+    static constexpr int WPE = (kProducers + NC) / 4;
     // thread-queue buffer: 64*T keys per query
     static constexpr int T = SelParams<KR>::T;
     // keys of one (query, chunk) row of partial results: a sorted queue, or
@@ -704,9 +718,11 @@ __device__ __forceinline__ void exchange_bounds(Sel& sel, const FusedArgs& a, in
 }
 
 template <class Op, int KR, int DP, bool VEC, bool L2>
-__global__ __launch_bounds__(64 * (kProducers + FusedShape<KR, DP * Op::BYTES>::NC))
-__attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
-    using S = FusedShape<KR, DP * Op::BYTES>;
+__global__ __launch_bounds__(64 * (kProducers + fused_consumers<Op, DP>())) __attribute__((
+    amdgpu_waves_per_eu((kProducers + fused_consumers<Op, DP>()) / 4,
+                        (kProducers + fused_consumers<Op, DP>()) / 4))) void
+knn_fused(FusedArgs args) {
+    using S = FusedShape<KR, DP * Op::BYTES, fused_consumers<Op, DP>()>;
     constexpr int T = S::T;
     constexpr int BQ = S::BQ, BN = S::BN, QW = S::QW, QPB = S::QPB, DPB = S::DPB, DG = S::DG;
     // Score slot: column-major, LDQ floats per database row (a multiple of 4,
@@ -735,15 +751,10 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
 
     __shared__ __align__(16) uint4 btile[NBUF][BN * GR];
     __shared__ __align__(16) float scores[2][BN * LDQ];
-    // per-row values of each tile the consumers need (||y||^2, 1/scale),
-    // staged by producer waves 0 (and 1) with the tile, so that consumers
-    // issue no global loads per step
-    constexpr int NY = (L2 ? 1 : 0) + (Op::SCALED ? 1 : 0);
-    __shared__ float ystage[NBUF][NY > 0 ? NY : 1][BN];
     // histogram bins of each consumer's pool selections: as many as the LDS
     // left over allows (at most 1024)
     constexpr int kLdsBytes = 160 * 1024;
-    constexpr int USED = NBUF * BN * GR * 16 + 2 * BN * LDQ * 4 + NBUF * (NY > 0 ? NY : 1) * BN * 4;
+    constexpr int USED = NBUF * BN * GR * 16 + 2 * BN * LDQ * 4;
     constexpr int NBINS = !S::mem_queues                             ? 1
                           : USED + S::NC * 1024 * 4 <= kLdsBytes     ? 1024
                           : USED + S::NC * 512 * 4 <= kLdsBytes      ? 512
@@ -783,16 +794,6 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
     }
     auto load_tile = [&](int64_t t0, int buf) {
         const bool tail = t0 + BN > c1;  // wave-uniform
-        if (wave < NY) {
-            const float* ysrc = (L2 && wave == 0) ? args.yn : args.yinv;
-            const int64_t row = t0 + lane < c1 ? t0 + lane : c1 - 1;
-            if constexpr (VEC) {
-                __builtin_amdgcn_global_load_lds((gbl_ptr_t)(ysrc + row), (lds_ptr_t)&ystage[buf][wave][0],
-                                                 4, 0, 0);
-            } else {
-                ystage[buf][wave][lane] = ysrc[row];
-            }
-        }
 #pragma unroll
         for (int t = 0; t < LPW; ++t) {
             int64_t row = t0 + lrow[t];
@@ -827,11 +828,7 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
         if (nsteps > 0) load_tile(c0, 0);
         if (NBUF == 3 && nsteps > 1) {
             load_tile(c0 + BN, 1);
-            // tile 0 has landed (waves < NY load one more value per tile)
-            if (wave < NY)
-                __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW + 1>());
-            else
-                __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW>());
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW>());  // tile 0 has landed
         } else {
             __builtin_amdgcn_s_waitcnt(0);
         }
@@ -895,9 +892,7 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
                 // next step's tile (and this step's score stores) must have
                 // landed; with three buffers the loads of the tile after it
                 // may stay in flight
-                if (NBUF == 3 && ahead < nsteps && wave < NY)
-                    __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW + 1>());
-                else if (NBUF == 3 && ahead < nsteps)
+                if (NBUF == 3 && ahead < nsteps)
                     __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW>());
                 else
                     __builtin_amdgcn_s_waitcnt(0);
@@ -933,9 +928,9 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
         }
         __syncthreads();
         float ynext = 0.f, ysnext = 1.f;
-        if (nsteps > 0) {
-            if (L2) ynext = ystage[0][0][lane];
-            if (Op::SCALED) ysnext = ystage[0][L2 ? 1 : 0][lane];
+        if (c0 + lane < c1) {
+            if (L2) ynext = args.yn[c0 + lane];
+            if (Op::SCALED) ysnext = args.yinv[c0 + lane];
         }
         for (int64_t s = 0; s <= nsteps; ++s) {
             if constexpr (S::mem_queues) {
@@ -959,10 +954,9 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_fused(FusedArgs args) {
                 const int64_t g = c0 + (s - 1) * BN + lane;
                 const bool ok = g < c1;
                 const float ynv = ynext, ysv = ysnext;
-                // tile s sits in buffer s % NBUF until step s + 1 reloads it
-                if (s < nsteps) {
-                    if (L2) ynext = ystage[s % NBUF][0][lane];
-                    if (Op::SCALED) ysnext = ystage[s % NBUF][L2 ? 1 : 0][lane];
+                if (g + BN < c1) {
+                    if (L2) ynext = args.yn[g + BN];
+                    if (Op::SCALED) ysnext = args.yinv[g + BN];
                 }
                 float score[QW];
                 const float* col = slot + lane * LDQ + cw * QW;

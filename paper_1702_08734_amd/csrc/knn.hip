@@ -57,7 +57,7 @@ template <int KR, int DP>
 mk_status knn_launch(const float* xq, int64_t nq, const float* xb, const float* yn, int64_t nb,
                      int32_t d, int32_t k, bool l2, bool vec, float* D, int64_t* I,
                      hipStream_t stream) {
-    using S = FusedShape<KR, DP * 4>;
+    using S = FusedShape<KR, DP * 4, fused_consumers<OpF32, DP>()>;
     constexpr int KS = 64 * KR;
     const int keff = k + kSlack < KS ? k + kSlack : KS;
     int64_t nqb, nchunks, chunk_len;

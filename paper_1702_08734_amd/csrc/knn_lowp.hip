@@ -80,7 +80,7 @@ mk_status lowp_launch(const float* xq, const void* xq_lp, const float* xq_inv, i
                       const float* xb, const void* xb_lp, const float* xb_inv, const float* yn,
                       int64_t nb, int32_t d, int32_t k, int32_t R, bool l2, float* D, int64_t* I,
                       hipStream_t stream) {
-    using S = FusedShape<KR, DP * Op::BYTES>;
+    using S = FusedShape<KR, DP * Op::BYTES, fused_consumers<Op, DP>()>;
     constexpr int KS = 64 * KR;
     int64_t nqb, nchunks, chunk_len;
     plan_chunks(nq, nb, S::BQ, S::BN, KS, &nqb, &nchunks, &chunk_len);
