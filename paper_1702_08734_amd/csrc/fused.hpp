@@ -20,12 +20,27 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 typedef __attribute__((address_space(1))) void* gbl_ptr_t;
 
 // ---------------------------------------------------------------- selectors
+// Chunks of one query tell each other how good their candidates are.  A
+// chunk that holds r candidates scoring at most v proves that r rows of the
+// database do; rows of different chunks are distinct, so once the proofs of
+// all chunks add up to keff rows scoring at most t, no candidate scoring
+// above t can enter the query's result.  Each chunk publishes four such
+// points (v at ranks r0, 2 r0, 4 r0 and keff of its queue, r0 = ceil(keff /
+// nchunks)); the tightest t that the published points prove is the query's
+// bound, which is near the keff-th score of everything its chunks have seen
+// so far, not merely of the best single chunk.
+constexpr int kRankPoints = 4;
+constexpr int kMaxRankChunks = 16;  // chunks per query when queues live in memory
+constexpr uint32_t kNoBound = 0xFFFFFFFFu;
+
 // QW independent selectors held by one wave (one per query the wave owns).
 // Each queue register r (and each thread-queue slot) is a vector over the QW
 // queries, low and high key halves apart, so that a merge can fetch and
 // store the state of one query chosen at run time with a wave-uniform index
 // (register-relative moves) instead of a select over all of them; the merge
-// network is emitted once, not once per query.
+// network is emitted once, not once per query.  A merge publishes the
+// queue's rank points (above).  Queries at or beyond nvalid never take
+// candidates.
 template <int KR, int T, int QW>
 struct MultiSelect {
     static constexpr int kQueries = QW;
@@ -33,30 +48,60 @@ struct MultiSelect {
     typedef float vqf __attribute__((ext_vector_type(QW)));
     vq wl[KR], wh[KR];   // wave queues
     vq tl[T], th[T];     // thread queues
-    vq kl, kh;           // key of each query's current k-th entry (wave-uniform)
-    vqf kf;              // its score, or the bound below if that is smaller
-    vqf bd;              // score bound from other database chunks
+    vq kl, kh;           // admission threshold key of each query (wave-uniform)
+    vqf kf;              // its score
+    vq bdu;              // order-mapped score bound from the chunks' rank points
     int cnt[QW];         // keys in each query's thread-queue buffer
-    int keff;
+    uint32_t* rpub;      // rank points of query q, this chunk, at rpub + q * rstride
+    int64_t rstride;
+    int rank[kRankPoints];
+    int keff, nvalid;
 
-    __device__ __forceinline__ void init(int k_eff) {
+    __device__ __forceinline__ void init(int k_eff, int valid, uint32_t* rank_base, int nchunks) {
         keff = k_eff;
+        nvalid = valid;
+        rpub = rank_base;
+        rstride = (int64_t)nchunks * kRankPoints;
+        const int r0 = (k_eff + nchunks - 1) / nchunks;
+        rank[0] = r0;
+        rank[1] = 2 * r0 < k_eff ? 2 * r0 : k_eff;
+        rank[2] = 4 * r0 < k_eff ? 4 * r0 : k_eff;
+        rank[3] = k_eff;
 #pragma unroll
         for (int r = 0; r < KR; ++r) wl[r] = wh[r] = ~0u;
 #pragma unroll
         for (int i = 0; i < T; ++i) tl[i] = th[i] = ~0u;
         kl = kh = ~0u;
         kf = INFINITY;
-        bd = INFINITY;
+        bdu = kNoBound;
 #pragma unroll
-        for (int q = 0; q < QW; ++q) cnt[q] = 0;
+        for (int q = 0; q < QW; ++q) {
+            cnt[q] = 0;
+            if (q >= valid) {  // never admits a candidate
+                kf[q] = -INFINITY;
+                kl[q] = kh[q] = 0u;
+            }
+        }
     }
 
-    // Candidates scoring above b cannot enter query q's result (another
-    // chunk already holds keff candidates scoring at most b).
-    __device__ __forceinline__ void bound(int q, float b) {
-        bd[q] = fminf(bd[q], b);
-        kf[q] = fminf(kf[q], b);
+    // Lower query q's admission threshold to kk or the bound, whichever is
+    // smaller; a candidate scoring exactly the bound still competes.
+    __device__ __forceinline__ void set_threshold(int q, uint64_t kk) {
+        const uint64_t bk = ((uint64_t)bdu[q] << 32) | 0xFFFFFFFFull;
+        const uint64_t cur = ((uint64_t)kh[q] << 32) | kl[q];
+        uint64_t th_key = kk < bk ? kk : bk;
+        th_key = th_key < cur ? th_key : cur;
+        kl[q] = (uint32_t)th_key;
+        kh[q] = (uint32_t)(th_key >> 32);
+        const uint32_t hi = (uint32_t)(th_key >> 32);
+        kf[q] = fminf(kf[q], hi == kNoBound ? INFINITY : order_float(hi));
+    }
+
+    __device__ __forceinline__ void bound_u(int q, uint32_t b) {
+        if (b < bdu[q]) {
+            bdu[q] = b;
+            set_threshold(q, ((uint64_t)kh[q] << 32) | kl[q]);
+        }
     }
 
     __device__ __forceinline__ uint64_t key(int q, int r) const {
@@ -84,14 +129,26 @@ struct MultiSelect {
         }
 #pragma unroll
         for (int qq = 0; qq < QW; ++qq) cnt[qq] = qq == q ? 0 : cnt[qq];
-        kl[q] = (uint32_t)kk;
-        kh[q] = (uint32_t)(kk >> 32);
-        kf[q] = fminf(kk == kSentinel ? INFINITY : key_score(kk), bd[q]);
+        set_threshold(q, kk);
+        if (rpub && q < nvalid) {
+            // the queue is sorted: its entry at rank r scores at most the
+            // published value, as do the r - 1 before it
+            const uint32_t p0 = (uint32_t)(ws_element<KR>(ww, rank[0] - 1) >> 32);
+            const uint32_t p1 = (uint32_t)(ws_element<KR>(ww, rank[1] - 1) >> 32);
+            const uint32_t p2 = (uint32_t)(ws_element<KR>(ww, rank[2] - 1) >> 32);
+            if (lane_id() == 0) {
+                uint64_t* rp = reinterpret_cast<uint64_t*>(rpub + (int64_t)q * rstride);
+                __hip_atomic_store(rp, ((uint64_t)p1 << 32) | p0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(rp + 1, ((uint64_t)(uint32_t)(kk >> 32) << 32) | p2,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
     }
 
     // Offer, for every query q, this lane's candidate (score[q], idx); ok
     // false means no candidate.  A query whose scores all lose to its current
-    // k-th score is skipped after one compare per lane.
+    // threshold is skipped after one compare per lane.
     __device__ __forceinline__ void offer(const float (&score)[QW], uint32_t idx, bool ok) {
         uint32_t full = 0;
 #pragma unroll
@@ -124,22 +181,9 @@ struct MultiSelect {
 
     __device__ __forceinline__ void finish() {
 #pragma unroll 1
-        for (int q = 0; q < QW; ++q) merge_slot(q);
+        for (int q = 0; q < nvalid; ++q) merge_slot(q);
     }
 };
-
-// Chunks of one query tell each other how good their candidates are.  A
-// chunk that holds r candidates scoring at most v proves that r rows of the
-// database do; rows of different chunks are distinct, so once the proofs of
-// all chunks add up to keff rows scoring at most t, no candidate scoring
-// above t can enter the query's result.  Each chunk publishes four such
-// points (v at ranks r0, 2 r0, 4 r0 and keff of its queue, r0 = ceil(keff /
-// nchunks)); the tightest t that the published points prove is the query's
-// bound, which is near the keff-th score of everything its chunks have seen
-// so far, not merely of the best single chunk.
-constexpr int kRankPoints = 4;
-constexpr int kMaxRankChunks = 16;  // chunks per query when queues live in memory
-constexpr uint32_t kNoBound = 0xFFFFFFFFu;
 
 // s_waitcnt immediate (gfx9 encoding) that waits for all LDS operations.
 constexpr int waitcnt_lgkm0() { return 0xF | (0x7 << 4) | (0x0 << 8) | (0x3 << 14); }
@@ -464,72 +508,62 @@ struct PoolSelect {
         }
     }
 
-    // Tighten every query's bound from the rank points all chunks have
-    // published (bound[q][c][0..3], at most kMaxRankChunks chunks).  G lanes
-    // serve one query: lane m proposes the points of chunks m, m + G, ... as
-    // bounds and counts, over every chunk, the rows each proposal is proven
-    // for; the smallest proposal proven for keff rows wins.
-    __device__ __forceinline__ void exchange(const uint32_t* bound, int nchunks, int64_t qfirst,
-                                             int64_t nq) {
-        constexpr int G = 64 / QW;
-        constexpr int CPL = kMaxRankChunks / G > 0 ? kMaxRankChunks / G : 1;
-        static_assert(G * QW == 64, "one query per G lanes");
-        const int lane = lane_id();
-        const int qq = lane / G, m = lane % G;
+};
+
+// Tighten every query's bound from the rank points all chunks have
+// published (bound[q][c][0..3], at most kMaxRankChunks chunks): each chunk's
+// points are proposed as bounds, the rows each proposal is proven for are
+// counted over every chunk, and the smallest proposal proven for keff rows
+// wins.  Here one lane per chunk serves a query, four queries per pass (few
+// registers, for the register-queue selectors).
+template <class Sel>
+__device__ __forceinline__ void exchange_ranks(Sel& sel, const uint32_t* bound, int nchunks,
+                                               int64_t qfirst, int64_t nq) {
+    constexpr int QW = Sel::kQueries;
+    constexpr int G = kMaxRankChunks;
+    constexpr int QPP = 64 / G;
+    static_assert(G * QPP == 64, "lanes per query");
+    const int lane = lane_id();
+    const int m = lane % G, sub = lane / G;
+#pragma unroll 1
+    for (int p = 0; p < (QW + QPP - 1) / QPP; ++p) {
+        const int qq = p * QPP + sub;
         const int64_t q = qfirst + qq;
-        const bool qok = q < nq;
-        const uint64_t* src = reinterpret_cast<const uint64_t*>(bound + (qok ? q : 0) * rstride);
-        uint32_t cand[CPL][kRankPoints];
-#pragma unroll
-        for (int u = 0; u < CPL; ++u) {
-            const int c = m + G * u;
-            uint64_t lo = ~0ull, hi = ~0ull;
-            if (qok && c < nchunks) {
-                lo = __hip_atomic_load(src + 2 * c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                hi = __hip_atomic_load(src + 2 * c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            cand[u][0] = (uint32_t)lo;
-            cand[u][1] = (uint32_t)(lo >> 32);
-            cand[u][2] = (uint32_t)hi;
-            cand[u][3] = (uint32_t)(hi >> 32);
+        const bool qok = qq < QW && q < nq;
+        uint32_t cand[kRankPoints];
+        uint64_t lo = ~0ull, hi = ~0ull;
+        if (qok && m < nchunks) {
+            const uint64_t* src = reinterpret_cast<const uint64_t*>(bound + q * sel.rstride) + 2 * m;
+            lo = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            hi = __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        int rows[CPL][kRankPoints];
+        cand[0] = (uint32_t)lo;
+        cand[1] = (uint32_t)(lo >> 32);
+        cand[2] = (uint32_t)hi;
+        cand[3] = (uint32_t)(hi >> 32);
+        int rows[kRankPoints] = {0, 0, 0, 0};
 #pragma unroll
-        for (int u = 0; u < CPL; ++u)
-#pragma unroll
-            for (int j = 0; j < kRankPoints; ++j) rows[u][j] = 0;
-        // chunk c's points are held by lane (qq * G + c % G), slot c / G
-#pragma unroll
-        for (int c = 0; c < kMaxRankChunks; ++c) {
+        for (int c = 0; c < G; ++c) {
             if (c < nchunks) {
-                const int from = qq * G + c % G;
+                const int from = sub * G + c;
                 uint32_t v[kRankPoints];
 #pragma unroll
-                for (int j = 0; j < kRankPoints; ++j)
-                    v[j] = (uint32_t)__shfl((int)cand[c / G][j], from);
+                for (int j = 0; j < kRankPoints; ++j) v[j] = (uint32_t)__shfl((int)cand[j], from);
 #pragma unroll
-                for (int u = 0; u < CPL; ++u) {
-                    if (G * u < nchunks) {
-#pragma unroll
-                        for (int j = 0; j < kRankPoints; ++j) {
-                            const uint32_t t = cand[u][j];
-                            const int add = v[3] <= t   ? rank[3]
-                                            : v[2] <= t ? rank[2]
-                                            : v[1] <= t ? rank[1]
-                                            : v[0] <= t ? rank[0]
-                                                        : 0;
-                            rows[u][j] += add;
-                        }
-                    }
+                for (int j = 0; j < kRankPoints; ++j) {
+                    const uint32_t t = cand[j];
+                    rows[j] += v[3] <= t   ? sel.rank[3]
+                               : v[2] <= t ? sel.rank[2]
+                               : v[1] <= t ? sel.rank[1]
+                               : v[0] <= t ? sel.rank[0]
+                                           : 0;
                 }
             }
         }
         uint32_t best = kNoBound;
 #pragma unroll
-        for (int u = 0; u < CPL; ++u)
-#pragma unroll
-            for (int j = 0; j < kRankPoints; ++j)
-                if (rows[u][j] >= keff && cand[u][j] < best) best = cand[u][j];
+        for (int j = 0; j < kRankPoints; ++j)
+            if (rows[j] >= sel.keff && cand[j] < best) best = cand[j];
 #pragma unroll
         for (int o = 1; o < G; o <<= 1) {
             const uint32_t other = (uint32_t)__shfl_xor((int)best, o);
@@ -537,9 +571,84 @@ struct PoolSelect {
         }
 #pragma unroll
         for (int j = 0; j < QW; ++j)
-            if (qfirst + j < nq) bound_u(j, (uint32_t)__builtin_amdgcn_readlane((int)best, j * G));
+            if (j / QPP == p && qfirst + j < nq)
+                sel.bound_u(j, (uint32_t)__builtin_amdgcn_readlane((int)best, (j % QPP) * G));
     }
-};
+}
+
+// One pass for all QW queries, 64 / QW lanes per query (lane m proposes the
+// points of chunks m, m + 64/QW, ...): fewer round trips, more registers.
+template <class Sel>
+__device__ __forceinline__ void exchange_ranks_wide(Sel& sel, const uint32_t* bound, int nchunks,
+                                                    int64_t qfirst, int64_t nq) {
+    constexpr int QW = Sel::kQueries;
+    constexpr int G = 64 / QW;
+    constexpr int CPL = kMaxRankChunks / G > 0 ? kMaxRankChunks / G : 1;
+    static_assert(G * QW == 64, "one query per G lanes");
+    const int lane = lane_id();
+    const int qq = lane / G, m = lane % G;
+    const int64_t q = qfirst + qq;
+    const bool qok = q < nq;
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(bound + (qok ? q : 0) * sel.rstride);
+    uint32_t cand[CPL][kRankPoints];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+        const int c = m + G * u;
+        uint64_t lo = ~0ull, hi = ~0ull;
+        if (qok && c < nchunks) {
+            lo = __hip_atomic_load(src + 2 * c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            hi = __hip_atomic_load(src + 2 * c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        cand[u][0] = (uint32_t)lo;
+        cand[u][1] = (uint32_t)(lo >> 32);
+        cand[u][2] = (uint32_t)hi;
+        cand[u][3] = (uint32_t)(hi >> 32);
+    }
+    int rows[CPL][kRankPoints];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+#pragma unroll
+        for (int j = 0; j < kRankPoints; ++j) rows[u][j] = 0;
+    // chunk c's points are held by lane (qq * G + c % G), slot c / G
+#pragma unroll
+    for (int c = 0; c < kMaxRankChunks; ++c) {
+        if (c < nchunks) {
+            const int from = qq * G + c % G;
+            uint32_t v[kRankPoints];
+#pragma unroll
+            for (int j = 0; j < kRankPoints; ++j)
+                v[j] = (uint32_t)__shfl((int)cand[c / G][j], from);
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) {
+                if (G * u < nchunks) {
+#pragma unroll
+                    for (int j = 0; j < kRankPoints; ++j) {
+                        const uint32_t t = cand[u][j];
+                        rows[u][j] += v[3] <= t   ? sel.rank[3]
+                                      : v[2] <= t ? sel.rank[2]
+                                      : v[1] <= t ? sel.rank[1]
+                                      : v[0] <= t ? sel.rank[0]
+                                                  : 0;
+                    }
+                }
+            }
+        }
+    }
+    uint32_t best = kNoBound;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+#pragma unroll
+        for (int j = 0; j < kRankPoints; ++j)
+            if (rows[u][j] >= sel.keff && cand[u][j] < best) best = cand[u][j];
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        const uint32_t other = (uint32_t)__shfl_xor((int)best, o);
+        best = other < best ? other : best;
+    }
+#pragma unroll
+    for (int j = 0; j < QW; ++j)
+        if (qfirst + j < nq) sel.bound_u(j, (uint32_t)__builtin_amdgcn_readlane((int)best, j * G));
+}
 
 // ---------------------------------------------------------------- operands
 // Operand formats of the distance tile.  A 16-byte granule holds EPG
@@ -679,43 +788,9 @@ struct FusedArgs {
     int64_t chunk_len;
     int32_t nchunks, nqb, keff;
     uint64_t* part;       // [nq][nchunks][ROW] keys: each chunk's queue (and pool)
-    // scores shared by the chunks of a query: rank points [nq][nchunks][4]
-    // when queues live in memory, else one order-mapped bound per query
+    // rank points shared by the chunks of a query, [nq][nchunks][4]
     uint32_t* bound;
 };
-
-// Chunks of one query with register queues share a bound on its selection
-// score: every
-// kBoundEvery steps a consumer tightens its queries' filters with the bound
-// published so far and publishes its own k-th score (a valid bound for every
-// chunk of the query: that chunk already holds keff candidates scoring at
-// most that much).  Scores equal to the bound still compete, so the kept set
-// is exactly the one without sharing.
-constexpr int kBoundEvery = 32;
-
-template <class Sel>
-__device__ __forceinline__ void exchange_bounds(Sel& sel, const FusedArgs& a, int64_t qfirst,
-                                                int lane) {
-    constexpr int QW = Sel::kQueries;
-    if (!a.bound) return;
-    // lane qq < QW handles query qfirst + qq: one load and one atomic per
-    // exchange for all of the consumer's queries
-    const int64_t q = qfirst + lane;
-    const bool mine_lane = lane < QW && q < a.nq;
-    uint32_t got = 0xFF800000u;  // order-mapped +inf
-    if (mine_lane) got = __hip_atomic_load(a.bound + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    float mine = INFINITY;
-#pragma unroll
-    for (int qq = 0; qq < QW; ++qq) {
-        if (qfirst + qq < a.nq)
-            sel.bound(qq, order_float((uint32_t)__builtin_amdgcn_readlane((int)got, qq)));
-        const float kq = sel.kf[qq];
-        mine = lane == qq ? kq : mine;
-    }
-    if (mine_lane && mine < INFINITY)
-        __hip_atomic_fetch_min(a.bound + q, float_order(mine + 0.0f), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-}
 
 template <class Op, int KR, int DP, bool VEC, bool L2>
 __global__ __launch_bounds__(64 * (kProducers + fused_consumers<Op, DP>())) __attribute__((
@@ -909,16 +984,16 @@ knn_fused(FusedArgs args) {
                                               MultiSelect<KR, T, QW>>::type;
         Sel sel;
         const int64_t qf = q0 + cw * QW;
+        const int64_t left = args.nq - qf;
+        const int nvalid = (int)(left < 0 ? 0 : left < QW ? left : QW);
+        uint32_t* ranks =
+            args.bound && left > 0 ? args.bound + (qf * args.nchunks + chunk) * kRankPoints : nullptr;
         if constexpr (S::mem_queues) {
-            const int64_t left = args.nq - qf;
             sel.init(args.keff, args.part + (qf * args.nchunks + chunk) * S::ROW,
-                     (int64_t)args.nchunks * S::ROW, (int)(left < 0 ? 0 : left < QW ? left : QW),
-                     args.bound && left > 0
-                         ? args.bound + (qf * args.nchunks + chunk) * kRankPoints
-                         : nullptr,
-                     args.nchunks, bins[S::mem_queues ? cw : 0]);
+                     (int64_t)args.nchunks * S::ROW, nvalid, ranks, args.nchunks,
+                     bins[S::mem_queues ? cw : 0]);
         } else {
-            sel.init(args.keff);
+            sel.init(args.keff, nvalid, ranks, args.nchunks);
         }
         float qs[QW];
 #pragma unroll
@@ -933,12 +1008,12 @@ knn_fused(FusedArgs args) {
             if (Op::SCALED) ysnext = args.yinv[c0 + lane];
         }
         for (int64_t s = 0; s <= nsteps; ++s) {
-            if constexpr (S::mem_queues) {
-                // often early, while the queues fill, then every 64 steps
-                if (args.bound && (s == 4 || s == 8 || s == 16 || s == 32 || (s & 63) == 0))
-                    sel.exchange(args.bound, args.nchunks, qf, args.nq);
-            } else if ((s & (kBoundEvery - 1)) == 0 || s == nsteps) {
-                exchange_bounds(sel, args, qf, lane);
+            // often early, while the queues fill, then every 64 steps
+            if (args.bound && (s == 4 || s == 8 || s == 16 || s == 32 || (s & 63) == 0)) {
+                if constexpr (S::mem_queues)
+                    exchange_ranks_wide(sel, args.bound, args.nchunks, qf, args.nq);
+                else
+                    exchange_ranks(sel, args.bound, args.nchunks, qf, args.nq);
             }
             if (s >= 1) {
                 if constexpr (S::mem_queues) {
@@ -991,7 +1066,6 @@ knn_fused(FusedArgs args) {
         }
         sel.finish();
         if constexpr (!S::mem_queues) {
-            exchange_bounds(sel, args, qf, lane);
 #pragma unroll
             for (int qq = 0; qq < QW; ++qq) {
                 const int64_t q = q0 + cw * QW + qq;
@@ -1010,18 +1084,18 @@ static __global__ void fill_bounds_kernel(uint32_t* __restrict__ bound, int64_t 
     if (i < n) bound[i] = v;
 }
 
-// Words of the bound array of a search with nchunks chunks.
+// Words of the rank-point array of a search with nchunks chunks.
 inline int64_t bound_words(int KR, int64_t nq, int64_t nchunks) {
-    return queues_in_memory(KR) ? nq * nchunks * kRankPoints : nq;
+    (void)KR;
+    return nq * nchunks * kRankPoints;
 }
 
-// No bound yet: rank points "no rows proven" (kNoBound), per-query bounds
-// order-mapped +inf.
+// No rank point yet: "no rows proven" (kNoBound).
 inline mk_status clear_bounds(int KR, uint32_t* bound, int64_t nq, int64_t nchunks, hipStream_t s) {
     const int64_t n = bound_words(KR, nq, nchunks);
     if (n == 0) return MK_OK;
     hipLaunchKernelGGL(fill_bounds_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, bound,
-                       n, queues_in_memory(KR) ? kNoBound : 0xFF800000u);
+                       n, kNoBound);
     MK_LAUNCHED();
     return MK_OK;
 }
@@ -1030,8 +1104,8 @@ inline mk_status clear_bounds(int KR, uint32_t* bound, int64_t nq, int64_t nchun
 // each fill their queue before shared bounds can help, so long queues get
 // fewer, longer chunks: about 4 workgroups per CU for queues of 512+ entries,
 // 16 otherwise, chunks of at least 32 queue lengths, at most kMaxRankChunks
-// chunks when queues live in memory, and among chunk counts within 25% of
-// that target the one whose last wave of workgroups is fullest.
+// chunks, and among chunk counts within 25% of that target the one whose
+// last wave of workgroups is fullest.
 inline void plan_chunks(int64_t nq, int64_t nb, int BQ, int BN, int KS, int64_t* nqb,
                         int64_t* nchunks, int64_t* chunk_len) {
     constexpr int64_t kCUs = 256;
@@ -1039,7 +1113,7 @@ inline void plan_chunks(int64_t nq, int64_t nb, int BQ, int BN, int KS, int64_t*
     const int64_t target = (KS >= 512 ? 4 : 16) * kCUs;
     const int64_t want = ceil_div(target, *nqb);
     int64_t max_by_len = nb / (32 * KS) > 1 ? nb / (32 * KS) : 1;
-    if (queues_in_memory(KS / 64) && max_by_len > kMaxRankChunks) max_by_len = kMaxRankChunks;
+    if (max_by_len > kMaxRankChunks) max_by_len = kMaxRankChunks;
     int64_t hi = want < max_by_len ? want : max_by_len;
     if (hi < 1) hi = 1;
     int64_t lo = (hi * 3) / 4 > 1 ? (hi * 3) / 4 : 1;
