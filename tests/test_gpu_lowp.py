@@ -74,20 +74,22 @@ def test_quantize_fp8_matches_torch(api, d):
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 @pytest.mark.parametrize("metric", ["l2", "ip"])
-def test_lowp_exact_on_representable_inputs(api, prec, metric):
+@pytest.mark.parametrize("nb,k,R", [(6000, 20, 80), (150_000, 100, 400)])
+def test_lowp_exact_on_representable_inputs(api, prec, metric, nb, k, R):
     # small integers are exact in BF16 and E4M3 (and the FP8 scale is a power
     # of two): every product and partial sum is exact in FP32, so the
-    # low-precision search equals the FP32 search exactly
-    say(f"lowp representable {prec} {metric}")
+    # low-precision search equals the FP32 search exactly -- also with many
+    # database chunks, memory-resident candidate pools and exact ties
+    say(f"lowp representable {prec} {metric} nb={nb} k={k} R={R}")
     rng = np.random.default_rng(3)
-    xb = rng.integers(-3, 4, size=(6000, 64)).astype(np.float32)
+    xb = rng.integers(-3, 4, size=(nb, 64)).astype(np.float32)
     xq = rng.integers(-3, 4, size=(70, 64)).astype(np.float32)
     xb[:, 0] = 3.0  # every row has max |x| = 3: one common FP8 scale
     xq[:, 0] = 3.0
     b = dev(xb)
     lp, inv = api.quantize_rows(b, prec)
-    D, I = api.knn_search_lowp(dev(xq), b, lp, inv, 20, 80, prec, metric)
-    De, Ie = api.knn_search(dev(xq), b, 20, metric)
+    D, I = api.knn_search_lowp(dev(xq), b, lp, inv, k, R, prec, metric)
+    De, Ie = api.knn_search(dev(xq), b, k, metric)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(I.cpu().numpy(), Ie.cpu().numpy())
     np.testing.assert_array_equal(D.cpu().numpy(), De.cpu().numpy())
