@@ -89,7 +89,11 @@ mk_status mk_kselect(const float* a, int64_t nrows, int64_t len, int32_t k, int3
  * The selection keeps extra candidates beyond k (up to the 1024-entry
  * selector) and re-ranks them by the direct form, which removes the
  * cancellation error of ||x||^2 + ||y||^2 - 2<x,y>.  nb must be < 2^31.
- * Supported d: 1..256.
+ * Supported d: 1..256.  Scratch (device): nq x nchunks x S keys of 8 bytes,
+ * nchunks <= 16, S = 64 R with R the smallest power of two such that 64 R
+ * >= min(k + 16, 1024), doubled when 64 R >= 256 (candidate pools); plus
+ * 16 bytes per (query, chunk) of shared rank points and, for L2 without
+ * supplied norms, 4 bytes per database row.
  */
 mk_status mk_knn_search(const float* xq, int64_t nq, const float* xb, int64_t nb, int32_t d,
                         int32_t k, mk_metric metric, float* D, int64_t* I, mk_stream_t stream);
