@@ -393,3 +393,68 @@ def test_ivfpq_train_shapes_and_objective():
                                        np.stack([np.arange(256) * 3, np.arange(256) * 5]))
     assert coarse.shape == (8, 8) and books.shape == (2, 256, 4)
     assert coarse.dtype == np.float32 and books.dtype == np.float32
+
+
+# ------------------------------------------------------------ training pins
+def test_ivfpq_train_lossless_fixture():
+    # quantizers known by construction (tests/train_fixture.py): training must
+    # return the two coarse centres and, per sub-space, the codewords of its
+    # init rows' residuals, bit for bit
+    from train_fixture import NLIST, M, build
+    f = build()
+    coarse, books = oracle.ivfpq_train(f["xt"], NLIST, M, 4, f["coarse_init"], f["pq_init"])
+    np.testing.assert_array_equal(coarse, f["coarse"])
+    np.testing.assert_array_equal(books, f["books"])
+
+
+def test_ivfpq_train_lossless_fixture_catches_planted_mistakes():
+    # each plausible mistake, planted in a copy of the oracle's training steps,
+    # fails the fixture: residuals to the initial coarse rows, a sub-vector
+    # slice off by one block, another sub-space's init rows
+    from train_fixture import DS, NLIST, M, build
+    f = build()
+    xt = f["xt"].astype(np.float64)
+
+    def train(residual_to_init=False, shift=0, same_init=False):
+        coarse, _ = oracle.kmeans(xt, f["coarse_init"], 4)
+        init = np.ascontiguousarray(xt[f["coarse_init"]], np.float32)
+        ref = init if residual_to_init else coarse
+        a, _ = oracle.kmeans_assign(xt, ref)
+        res = xt - ref[a].astype(np.float64)
+        books = np.empty((M, 256, DS), np.float32)
+        for m in range(M):
+            mm = (m + shift) % M
+            sub = np.ascontiguousarray(res[:, mm * DS:(mm + 1) * DS])
+            rows = f["pq_init"][0 if same_init else m]
+            books[m], _ = oracle.kmeans(sub, rows, 4)
+        return books
+
+    np.testing.assert_array_equal(train(), f["books"])  # the copy is faithful
+    for bad in ({"residual_to_init": True}, {"shift": 1}, {"same_init": True}):
+        assert not np.array_equal(train(**bad), f["books"]), bad
+
+
+def test_ivfpq_train_residuals_to_final_centroids_handworked(golden_dir):
+    with open(os.path.join(golden_dir, "ivfpq_train_handworked.json")) as fh:
+        g = json.load(fh)
+    i = np.arange(256, dtype=np.float64)
+    xt = np.stack([i, 2 * i, -i, 3 * i], axis=1).astype(np.float32)
+    pq_init = np.array([[(5 * j + 3 * m) % 256 for j in range(256)] for m in range(4)], np.int64)
+    coarse, books = oracle.ivfpq_train(xt, g["nlist"], g["M"], g["niter"], g["coarse_init"],
+                                       pq_init)
+    assert coarse.tolist() == g["coarse"]
+    for e in g["books_sample"]:
+        assert books[e["m"], e["j"], 0] == e["value"], e
+
+
+def test_kmeans_loop_1d_handworked(golden_dir):
+    # the Lloyd loop itself (Forgy rows 0 and 1) reproduces the hand-worked
+    # iterations: objective measured at each assignment, final centroids
+    g = _load(golden_dir, "kmeans_1d.json")
+    x = np.array(g["points"], np.float64)
+    n = len(g["iterations"])
+    c, objs = oracle.kmeans(x, [0, 1], n)
+    assert g["init"] == [x[0].tolist(), x[1].tolist()]
+    # objectives are measured against FP32-rounded centroids (7.3333335)
+    np.testing.assert_allclose(objs, [it["objective"] for it in g["iterations"]], rtol=1e-6)
+    np.testing.assert_allclose(c, np.array(g["iterations"][-1]["centroids"]), rtol=1e-7)
