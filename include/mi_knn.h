@@ -307,8 +307,9 @@ mk_status mk_mlp_set_params(mk_mlp* net, const float* theta);
  * NULL).  Synchronises. */
 mk_status mk_mlp_get_params(const mk_mlp* net, float* theta, float* grad);
 
-/* Per-column mean and population standard deviation (FP64 sums; a column
- * without spread gets deviation 1) of n raw feature rows F [n, din]. */
+/* Per-column mean and population standard deviation of n raw feature rows
+ * F [n, din] (device), summed in FP64 on the host after one copy of F (a
+ * column without spread gets deviation 1).  Synchronises. */
 mk_status mk_mlp_fit_standardization(mk_mlp* net, const float* F, int64_t n,
                                      mk_stream_t stream);
 
@@ -425,6 +426,16 @@ mk_status mk_server_stats(mk_server* server, int64_t* batches, int64_t* rows);
 
 /* Finish every queued request, stop the threads, free the buffers. */
 void mk_server_destroy(mk_server* server);
+
+/*
+ * Debug check of the candidate pools of the fused exact search (queues of 256
+ * entries and more, Section 4.2's selection replaced by an unsorted pool cut
+ * back by radix selection): the number of candidates, over every search on
+ * the current device since the library was loaded, that a full pool had to
+ * drop.  Pools are cut before they can fill, so the count is 0 unless the
+ * selection is broken.  Synchronises the device.
+ */
+mk_status mk_debug_pool_drops(int64_t* count);
 
 /* ------------------------------------------------------------------------
  * Kernel timing.  While enabled, every launch of the library's main kernels

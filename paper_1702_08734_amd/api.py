@@ -79,6 +79,7 @@ _SIGS = {
     "mk_server_wait": [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)],
     "mk_server_stats": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
     "mk_server_destroy": [_vp],
+    "mk_debug_pool_drops": [ctypes.POINTER(_i64)],
     "mk_profile_enable": [_i32],
     "mk_profile_read": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)],
 }
@@ -353,6 +354,13 @@ class IVFPQ:
         ids = np.empty(max(n, 1), np.int64)
         _call("mk_ivfpq_get_lists", self._h, offs.ctypes.data, codes.ctypes.data, ids.ctypes.data)
         return offs, codes[:n], ids[:n]
+
+
+def debug_pool_drops() -> int:
+    """Candidates dropped by full candidate pools so far (must be 0)."""
+    n = _i64()
+    _call("mk_debug_pool_drops", ctypes.byref(n))
+    return n.value
 
 
 def profile_enable(on: bool = True) -> None:

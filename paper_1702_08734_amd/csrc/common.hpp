@@ -49,17 +49,40 @@ const char* get_error();
         if (st_ != MK_OK) return st_; \
     } while (0)
 
-// Stream-ordered device scratch; freed on the same stream when it goes out of
-// scope, so a call never synchronises to release it.
+// A caller-provided block of device memory that scratch buffers are carved
+// from in order (256-byte aligned) instead of being allocated.
+struct Arena {
+    unsigned char* base = nullptr;
+    size_t size = 0;
+    size_t used = 0;
+};
+
+// Device scratch: stream-ordered allocations freed on the same stream when
+// they go out of scope (so a call never synchronises to release them), or,
+// with an arena, a slice of the arena that is never freed.
 struct Scratch {
     void* ptr = nullptr;
     hipStream_t stream = nullptr;
+    bool owned = false;
     Scratch() = default;
     Scratch(const Scratch&) = delete;
     Scratch& operator=(const Scratch&) = delete;
-    mk_status alloc(size_t bytes, hipStream_t s) {
+    mk_status alloc(size_t bytes, hipStream_t s, Arena* arena = nullptr) {
         stream = s;
         if (bytes == 0) bytes = 256;
+        if (arena) {
+            const size_t start = (arena->used + 255) & ~(size_t)255;
+            if (start > arena->size || bytes > arena->size - start) {
+                set_error("scratch of " + std::to_string(bytes) + " bytes does not fit the " +
+                          std::to_string(arena->size) + "-byte workspace (" +
+                          std::to_string(start) + " bytes already used)");
+                return MK_ERR_UNSUPPORTED;
+            }
+            ptr = arena->base + start;
+            arena->used = start + bytes;
+            owned = false;
+            return MK_OK;
+        }
         hipError_t e = hipMallocAsync(&ptr, bytes, s);
         if (e != hipSuccess) {
             ptr = nullptr;
@@ -67,12 +90,13 @@ struct Scratch {
                       " bytes failed: " + hipGetErrorString(e));
             return e == hipErrorOutOfMemory ? MK_ERR_OOM : MK_ERR_DEVICE;
         }
+        owned = true;
         return MK_OK;
     }
     template <class T>
     T* as() const { return static_cast<T*>(ptr); }
     ~Scratch() {
-        if (ptr) (void)hipFreeAsync(ptr, stream);
+        if (ptr && owned) (void)hipFreeAsync(ptr, stream);
     }
 };
 

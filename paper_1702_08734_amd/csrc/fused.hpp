@@ -253,12 +253,15 @@ struct PoolSelect {
     uint32_t* rpub;      // rank points of query q, this chunk, at rpub + q * rstride
     int64_t rstride;
     uint32_t* hist;      // NB zeroed counters in LDS, private to this wave
+    unsigned long long* drops;  // keys an overfull pool could not hold (stays 0)
     int rank[kRankPoints];
     int keff, nvalid;
 
     __device__ __forceinline__ void init(int k_eff, uint64_t* base, int64_t stride, int valid,
-                                         uint32_t* rank_base, int nchunks, uint32_t* bins) {
+                                         uint32_t* rank_base, int nchunks, uint32_t* bins,
+                                         unsigned long long* drop_count) {
         keff = k_eff;
+        drops = drop_count;
         wbase = base;
         wstride = stride;
         nvalid = valid;
@@ -453,7 +456,12 @@ struct PoolSelect {
                 if (bal) {
                     const int below = (int)__builtin_amdgcn_mbcnt_hi(
                         (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                    if (take && cnt[q] + below < CAP) wbase[(int64_t)q * wstride + cnt[q] + below] = key;
+                    if (take) {
+                        if (cnt[q] + below < CAP)
+                            wbase[(int64_t)q * wstride + cnt[q] + below] = key;
+                        else if (drops)  // refine_pools() runs first: never taken
+                            atomicAdd(drops, 1ull);
+                    }
                     cnt[q] += __popcll(bal);
                 }
             }
@@ -790,6 +798,8 @@ struct FusedArgs {
     uint64_t* part;       // [nq][nchunks][ROW] keys: each chunk's queue (and pool)
     // rank points shared by the chunks of a query, [nq][nchunks][4]
     uint32_t* bound;
+    // debug count of candidates a full pool had to drop (must stay zero)
+    unsigned long long* drops;
 };
 
 template <class Op, int KR, int DP, bool VEC, bool L2>
@@ -991,7 +1001,7 @@ knn_fused(FusedArgs args) {
         if constexpr (S::mem_queues) {
             sel.init(args.keff, args.part + (qf * args.nchunks + chunk) * S::ROW,
                      (int64_t)args.nchunks * S::ROW, nvalid, ranks, args.nchunks,
-                     bins[S::mem_queues ? cw : 0]);
+                     bins[S::mem_queues ? cw : 0], args.drops);
         } else {
             sel.init(args.keff, nvalid, ranks, args.nchunks);
         }

@@ -507,11 +507,11 @@ __global__ void entry_term1_kernel(const int64_t* __restrict__ offsets, int32_t 
 // scanned entry's ADC distance is term 2 (the coarse distance of its list)
 // + its stored term 1 + the M table lookups of its code bytes (Eq. 10-11).
 // Waves take 64 entries at a time, list by list, into WaveSelect queues keyed
-// (distance, list slot << 28 | offset); the 4 queues are merged, and the
-// winners' ids are resolved so that the partial list is keyed (distance, id).
+// (distance, id), the id being read only for entries that beat the queue's
+// current threshold (Section 5.3 resolves ids only for selected entries);
+// the 4 queues are merged into the group's partial list.
 // Item -> (query, group): fixed probe count nprobe (= ld) when work is null,
 // else query q owns items work[q] .. work[q + 1] - 1 and probes tau[q] lists.
-constexpr int kSlotShift = 28;
 
 template <int KR>
 __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
@@ -569,6 +569,7 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
         const int64_t n = offsets[L + 1] - lo;
         const uint8_t* lc = codes + lo * M;
         const float* lt = t1e + lo;
+        const int64_t* lid = ids + lo;
 #pragma unroll 1
         for (int64_t e0 = (int64_t)wave * 64; e0 < n; e0 += 64 * kScanWaves) {
             const int64_t e = e0 + lane;
@@ -598,8 +599,11 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
                     }
                 }
             }
-            const uint64_t key =
-                ok ? make_key(dist, ((uint32_t)sl << kSlotShift) | (uint32_t)e) : kSentinel;
+            // keyed (distance, id): ids are unique, so the order is total and
+            // the selected set does not depend on how lists are grouped; the
+            // id is read only for an entry that can enter the queue
+            uint64_t key = kSentinel;
+            if (ok && ws.may_take(dist)) key = make_key(dist, (uint32_t)lid[e]);
             if (ws.push(key)) ws.merge();
         }
     }
@@ -625,17 +629,7 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
 #pragma unroll
         for (int r = 0; r < KR; ++r) {
             const int e = r * 64 + lane;
-            if (e < k) {
-                const uint64_t key = fin.w[r];
-                uint64_t o = kSentinel;
-                if (key != kSentinel) {
-                    const uint32_t v = key_index(key);
-                    const int64_t L = cirow[v >> kSlotShift];
-                    const int64_t id = ids[offsets[L] + (v & ((1u << kSlotShift) - 1))];
-                    o = (key & 0xFFFFFFFF00000000ull) | (uint32_t)id;
-                }
-                out[e] = o;
-            }
+            if (e < k) out[e] = fin.w[r];
         }
     }
 }
@@ -797,9 +791,6 @@ mk_status add(mk_ivfpq* ix, const float* xb, int64_t nb, hipStream_t s) {
     }
     const int64_t total = no[nlist];
     MK_REQUIRE(total < (1ll << 32) - 1, MK_ERR_UNSUPPORTED, "an index holds fewer than 2^32 - 1 vectors");
-    for (int32_t L = 0; L < nlist; ++L)
-        MK_REQUIRE(no[L + 1] - no[L] < (1ll << kSlotShift), MK_ERR_UNSUPPORTED,
-                   "an inverted list holds fewer than 2^28 entries");
     uint8_t* ncodes = nullptr;
     int64_t* nids = nullptr;
     MK_TRY(alloc_dev(ncodes, (size_t)total * M));

@@ -18,11 +18,12 @@
 //      and re-ranks them.  The selection keeps k + 16 candidates (when the
 //      1024-entry queue allows) so that the FP32 cancellation of the norm
 //      decomposition cannot push a true neighbour out of the final k.
+#include <mutex>
+#include <vector>
+
 #include "fused.hpp"
 
 namespace mk {
-
-constexpr int kSlack = 16;
 
 // ---------------------------------------------------------------- norms
 __global__ __launch_bounds__(256) void norms_kernel(const float* __restrict__ x, int64_t n,
@@ -53,60 +54,31 @@ mk_status launch_norms(const float* x, int64_t n, int32_t d, float* out, hipStre
 }
 
 
-template <int KR, int DP>
-mk_status knn_launch(const float* xq, int64_t nq, const float* xb, const float* yn, int64_t nb,
-                     int32_t d, int32_t k, bool l2, bool vec, float* D, int64_t* I,
-                     hipStream_t stream) {
-    using S = FusedShape<KR, DP * 4, fused_consumers<OpF32, DP>()>;
-    constexpr int KS = 64 * KR;
-    const int keff = k + kSlack < KS ? k + kSlack : KS;
-    int64_t nqb, nchunks, chunk_len;
-    plan_chunks(nq, nb, S::BQ, S::BN, KS, &nqb, &nchunks, &chunk_len);
-
-    Scratch part, bound;
-    mk_status st = part.alloc(sizeof(uint64_t) * (size_t)nq * (size_t)nchunks * S::ROW, stream);
-    if (st != MK_OK) return st;
-    MK_TRY(bound.alloc(sizeof(uint32_t) * (size_t)bound_words(KR, nq, nchunks), stream));
-    MK_TRY(clear_bounds(KR, bound.as<uint32_t>(), nq, nchunks, stream));
-    const int64_t nblocks = nqb * nchunks;
-    MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
-    FusedArgs a{xq, xb, yn, nullptr, nullptr, nq, nb, d, d, chunk_len, (int32_t)nchunks,
-                (int32_t)nqb, keff, part.as<uint64_t>(), bound.as<uint32_t>()};
-    {
-        ProfScope prof("knn_fused", stream);
-        auto kern = vec ? (l2 ? knn_fused<OpF32, KR, DP, true, true> : knn_fused<OpF32, KR, DP, true, false>)
-                        : (l2 ? knn_fused<OpF32, KR, DP, false, true> : knn_fused<OpF32, KR, DP, false, false>);
-        hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(64 * (kProducers + S::NC)), 0, stream, a);
-        MK_LAUNCHED();
-    }
-    {
-        ProfScope prof("knn_merge_rerank", stream);
-        hipLaunchKernelGGL((knn_merge_rerank<KR>), dim3((unsigned)ceil_div(nq, kMergeWaves)),
-                           dim3(64 * kMergeWaves), 0, stream, part.as<uint64_t>(),
-                           (int32_t)nchunks, (int32_t)S::ROW, S::mem_queues ? KS : keff, xq, nq,
-                           xb, d, (int32_t)vec, (int32_t)l2, k, keff, D, I);
-        MK_LAUNCHED();
-    }
-    return MK_OK;
-}
-
+// Fused search for padded dimension class DP (knn_impl.hpp, one translation
+// unit per class).
 template <int DP>
 mk_status knn_dispatch_k(const float* xq, int64_t nq, const float* xb, const float* yn,
                          int64_t nb, int32_t d, int32_t k, bool l2, bool vec, float* D, int64_t* I,
-                         hipStream_t s) {
-    const int want = k + kSlack < kMaxK ? k + kSlack : kMaxK;
-    switch (queue_regs(want)) {
-        case 1: return knn_launch<1, DP>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
-        case 2: return knn_launch<2, DP>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
-        case 4: return knn_launch<4, DP>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
-        case 8: return knn_launch<8, DP>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
-        default: return knn_launch<16, DP>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
-    }
-}
+                         hipStream_t s, Arena* arena);
+extern template mk_status knn_dispatch_k<32>(const float*, int64_t, const float*, const float*,
+                                              int64_t, int32_t, int32_t, bool, bool, float*,
+                                              int64_t*, hipStream_t, Arena*);
+extern template mk_status knn_dispatch_k<64>(const float*, int64_t, const float*, const float*,
+                                              int64_t, int32_t, int32_t, bool, bool, float*,
+                                              int64_t*, hipStream_t, Arena*);
+extern template mk_status knn_dispatch_k<96>(const float*, int64_t, const float*, const float*,
+                                              int64_t, int32_t, int32_t, bool, bool, float*,
+                                              int64_t*, hipStream_t, Arena*);
+extern template mk_status knn_dispatch_k<128>(const float*, int64_t, const float*, const float*,
+                                               int64_t, int32_t, int32_t, bool, bool, float*,
+                                               int64_t*, hipStream_t, Arena*);
+extern template mk_status knn_dispatch_k<256>(const float*, int64_t, const float*, const float*,
+                                               int64_t, int32_t, int32_t, bool, bool, float*,
+                                               int64_t*, hipStream_t, Arena*);
 
 mk_status knn_search(const float* xq, int64_t nq, const float* xb, const float* yn_in, int64_t nb,
                      int32_t d, int32_t k, mk_metric metric, float* D, int64_t* I,
-                     hipStream_t s) {
+                     hipStream_t s, Arena* arena) {
     MK_REQUIRE(nq >= 0 && nb >= 0, MK_ERR_INVALID_ARG, "nq and nb must be >= 0");
     MK_REQUIRE(d >= 1, MK_ERR_INVALID_ARG, "d must be >= 1");
     MK_REQUIRE(k >= 1, MK_ERR_INVALID_ARG, "k must be >= 1");
@@ -122,18 +94,43 @@ mk_status knn_search(const float* xq, int64_t nq, const float* xb, const float* 
     Scratch norms;
     const float* yn = yn_in;
     if (l2 && !yn && nb > 0) {
-        mk_status st = norms.alloc(sizeof(float) * (size_t)nb, s);
+        mk_status st = norms.alloc(sizeof(float) * (size_t)nb, s, arena);
         if (st != MK_OK) return st;
         st = launch_norms(xb, nb, d, norms.as<float>(), s);
         if (st != MK_OK) return st;
         yn = norms.as<float>();
     }
-    if (d <= 32) return knn_dispatch_k<32>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
-    if (d <= 64) return knn_dispatch_k<64>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
-    if (d <= 96) return knn_dispatch_k<96>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
-    if (d <= 128) return knn_dispatch_k<128>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
-    return knn_dispatch_k<256>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s);
+    if (d <= 32) return knn_dispatch_k<32>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s, arena);
+    if (d <= 64) return knn_dispatch_k<64>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s, arena);
+    if (d <= 96) return knn_dispatch_k<96>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s, arena);
+    if (d <= 128) return knn_dispatch_k<128>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s, arena);
+    return knn_dispatch_k<256>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s, arena);
 }
+
+// ------------------------------------------------- device symbols
+// Count of candidates dropped by full candidate pools (debug; stays zero).
+static __device__ unsigned long long pool_drops;
+
+namespace {
+std::mutex g_sym_mu;
+std::vector<unsigned long long*> g_drops_dev;  // per device id; null until looked up
+}  // namespace
+
+mk_status pool_drop_counter(unsigned long long** out) {
+    int dev = 0;
+    MK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_sym_mu);
+    if ((int)g_drops_dev.size() <= dev) g_drops_dev.resize(dev + 1, nullptr);
+    if (!g_drops_dev[dev]) {
+        void* p = nullptr;
+        MK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(pool_drops)));
+        MK_REQUIRE(p, MK_ERR_DEVICE, "no device address for the pool-drop counter");
+        g_drops_dev[dev] = static_cast<unsigned long long*>(p);
+    }
+    *out = g_drops_dev[dev];
+    return MK_OK;
+}
+
 
 template <int KR>
 mk_status rerank_launch(const uint64_t* keys, int64_t nq, int32_t R, const float* xq,
@@ -189,4 +186,18 @@ extern "C" mk_status mk_knn_search_prenorm(const float* xq, int64_t nq, const fl
                "L2 search needs the database norms");
     return mk::knn_search(xq, nq, xb, yn, nb, d, k, metric, D, I,
                           static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_debug_pool_drops(int64_t* count) {
+    MK_REQUIRE(count, MK_ERR_INVALID_ARG, "null pointer");
+    unsigned long long* p = nullptr;
+    {
+        mk_status st = mk::pool_drop_counter(&p);
+        if (st != MK_OK) return st;
+    }
+    unsigned long long v = 0;
+    MK_HIP(hipDeviceSynchronize());
+    MK_HIP(hipMemcpy(&v, p, sizeof(v), hipMemcpyDeviceToHost));
+    *count = (int64_t)v;
+    return MK_OK;
 }

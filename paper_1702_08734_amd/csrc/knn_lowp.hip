@@ -44,13 +44,25 @@ __global__ __launch_bounds__(256) void quantize_rows_kernel(const float* __restr
         for (int t = lane; t < d; t += 64) m = fmaxf(m, fabsf(xr[t]));
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-        double sc = 1.0;
+        // s = the largest power of two with m s <= 448 = 1.75 * 2^8, from the
+        // bits of m = f 2^e (f in [1, 2)): 2^(8-e) when f <= 1.75, else
+        // 2^(7-e); either way m s lands in (224, 448].  s is capped at 2^126
+        // (rows with max |x| under 2^-118, subnormal ones included, keep m s
+        // below 224) so that s and 1/s are normal floats built exactly from
+        // their exponent fields.
+        float s = 1.f, inv = 1.f;
         if (m > 0.f) {
-            int e;
-            frexp(448.0 / (double)m, &e);  // 448/m = f 2^e, f in [0.5, 1)
-            sc = ldexp(1.0, e - 1);        // largest power of two <= 448/m
+            const uint32_t bits = __float_as_uint(m);
+            const int field = (int)((bits >> 23) & 0xFF);
+            int p = 126;
+            if (field > 0) {
+                const uint32_t frac = bits & 0x7FFFFF;  // f = 1 + frac 2^-23
+                p = (frac <= 0x600000u ? 8 : 7) - (field - 127);  // 0x600000: f = 1.75
+                p = p > 126 ? 126 : p;
+            }
+            s = __uint_as_float((uint32_t)(p + 127) << 23);
+            inv = __uint_as_float((uint32_t)(127 - p) << 23);
         }
-        const float s = (float)sc;
         uint16_t* o = reinterpret_cast<uint16_t*>(static_cast<uint8_t*>(out) + row * ld);
         for (int t2 = lane; 2 * t2 < ld; t2 += 64) {
             const int t = 2 * t2;
@@ -58,7 +70,7 @@ __global__ __launch_bounds__(256) void quantize_rows_kernel(const float* __restr
             const float b = t + 1 < d ? xr[t + 1] * s : 0.f;
             o[t2] = (uint16_t)(__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xFFFF);
         }
-        if (inv_scale && lane == 0) inv_scale[row] = (float)(1.0 / sc);
+        if (inv_scale && lane == 0) inv_scale[row] = inv;
     }
 }
 
@@ -92,8 +104,10 @@ mk_status lowp_launch(const float* xq, const void* xq_lp, const float* xq_inv, i
     const int64_t nblocks = nqb * nchunks;
     MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
     const int32_t ld = lowp_stride(d);
+    unsigned long long* drops = nullptr;
+    MK_TRY(pool_drop_counter(&drops));
     FusedArgs a{xq_lp, xb_lp, yn, xq_inv, xb_inv, nq, nb, ld, ld, chunk_len, (int32_t)nchunks,
-                (int32_t)nqb, R, part.as<uint64_t>(), bound.as<uint32_t>()};
+                (int32_t)nqb, R, part.as<uint64_t>(), bound.as<uint32_t>(), drops};
     {
         ProfScope prof(Op::SCALED ? "knn_fused_fp8" : "knn_fused_bf16", stream);
         auto kern = l2 ? knn_fused<Op, KR, DP, true, true> : knn_fused<Op, KR, DP, true, false>;

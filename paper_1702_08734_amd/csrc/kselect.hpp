@@ -41,10 +41,18 @@ mk_status merge_key_lists(const uint64_t* partial, int64_t nrows, int32_t nseg, 
                           uint64_t* keys_out = nullptr, const int64_t* seg_offs = nullptr);
 
 // Exact k-NN (knn.hip); yn may be null (then computed) for L2.
+// With an arena every scratch buffer is carved from it (nothing is
+// allocated); a workspace too small gives MK_ERR_UNSUPPORTED.
+struct Arena;
 mk_status knn_search(const float* xq, int64_t nq, const float* xb, const float* yn, int64_t nb,
                      int32_t d, int32_t k, mk_metric metric, float* D, int64_t* I,
-                     hipStream_t s);
+                     hipStream_t s, Arena* arena = nullptr);
 mk_status launch_norms(const float* x, int64_t n, int32_t d, float* out, hipStream_t s);
+
+// Device address (current device) of the library's count of candidates that
+// a full candidate pool of the fused kernel had to drop.  The pools are cut
+// before they can overflow, so the count stays zero; it is a debug check.
+mk_status pool_drop_counter(unsigned long long** out);
 
 // Exact re-rank of candidate lists: keys[row] holds 64 * queue_regs(R) keys
 // whose first R are the row's candidates (score, database row); each

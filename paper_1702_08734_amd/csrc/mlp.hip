@@ -286,46 +286,6 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
     p[i] -= lr * (a / bc1) / (sqrtf(b / bc2) + eps);
 }
 
-// Column mean and population standard deviation in FP64 (zero spread -> 1):
-// a workgroup per 64 columns, 16 row groups and a fixed tree, two passes.
-__global__ __launch_bounds__(64 * kColRows) void stats_kernel(const float* __restrict__ F,
-                                                              int64_t n, int32_t din,
-                                                              float* __restrict__ mean,
-                                                              float* __restrict__ inv_std) {
-    __shared__ double part[kColRows][64];
-    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int t = blockIdx.x * 64 + c;
-    double s = 0.0;
-    if (t < din)
-        for (int64_t i = g; i < n; i += kColRows) s += (double)F[i * din + t];
-    part[g][c] = s;
-    __syncthreads();
-    for (int w = kColRows / 2; w >= 1; w >>= 1) {
-        if (g < w) part[g][c] += part[g + w][c];
-        __syncthreads();
-    }
-    const double mu = part[0][c] / (double)n;
-    __syncthreads();
-    double v = 0.0;
-    if (t < din)
-        for (int64_t i = g; i < n; i += kColRows) {
-            const double d = (double)F[i * din + t] - mu;
-            v += d * d;
-        }
-    part[g][c] = v;
-    __syncthreads();
-    for (int w = kColRows / 2; w >= 1; w >>= 1) {
-        if (g < w) part[g][c] += part[g + w][c];
-        __syncthreads();
-    }
-    if (g == 0 && t < din) {
-        double sd = sqrt(part[0][c] / (double)n);
-        if (sd == 0.0) sd = 1.0;
-        mean[t] = (float)mu;
-        inv_std[t] = (float)(1.0 / sd);
-    }
-}
-
 // Work buffers of one pass over B rows.
 struct Pass {
     Scratch xs, h1, h2, yhat, dy, dz2, dz1, loss;
@@ -517,10 +477,34 @@ extern "C" mk_status mk_mlp_fit_standardization(mk_mlp* net, const float* F, int
                                                 mk_stream_t stream) {
     MK_REQUIRE(net && F, MK_ERR_INVALID_ARG, "null pointer");
     MK_REQUIRE(n >= 1, MK_ERR_INVALID_ARG, "need n >= 1");
-    hipLaunchKernelGGL(mk::stats_kernel, dim3((unsigned)mk::ceil_div(net->din, 64)),
-                       dim3(64 * mk::kColRows), 0, static_cast<hipStream_t>(stream), F, n, net->din,
-                       net->mean, net->inv_std);
-    MK_LAUNCHED();
+    // A one-off preparation step of training, not part of any search: the
+    // rows are copied to the host and the statistics summed there in FP64
+    // (two passes, rows in order), so the device runs no FP64 arithmetic.
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t din = net->din;
+    std::vector<float> h((size_t)n * din);
+    MK_HIP(hipMemcpyAsync(h.data(), F, sizeof(float) * h.size(), hipMemcpyDeviceToHost, s));
+    MK_HIP(hipStreamSynchronize(s));
+    std::vector<double> mu(din, 0.0), var(din, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t t = 0; t < din; ++t) mu[t] += (double)h[(size_t)i * din + t];
+    for (int32_t t = 0; t < din; ++t) mu[t] /= (double)n;
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t t = 0; t < din; ++t) {
+            const double d = (double)h[(size_t)i * din + t] - mu[t];
+            var[t] += d * d;
+        }
+    std::vector<float> mean(din), inv(din);
+    for (int32_t t = 0; t < din; ++t) {
+        double sd = std::sqrt(var[t] / (double)n);
+        if (sd == 0.0) sd = 1.0;
+        mean[t] = (float)mu[t];
+        inv[t] = (float)(1.0 / sd);
+    }
+    MK_HIP(hipMemcpyAsync(net->mean, mean.data(), sizeof(float) * din, hipMemcpyHostToDevice, s));
+    MK_HIP(hipMemcpyAsync(net->inv_std, inv.data(), sizeof(float) * din, hipMemcpyHostToDevice,
+                          s));
+    MK_HIP(hipStreamSynchronize(s));
     return MK_OK;
 }
 

@@ -295,7 +295,9 @@ extern "C" mk_status mk_server_wait(mk_server* sv, uint64_t ticket, double* late
         MK_REQUIRE(it != sv->live.end(), MK_ERR_INVALID_ARG, "unknown or already collected ticket");
         r = it->second;
         sv->cv_done.wait(lk, [&] { return r->done; });
-        sv->live.erase(it);
+        // submissions may have rehashed the map while the lock was released
+        // inside wait(): erase by key, not through the old iterator
+        sv->live.erase(ticket);
     }
     if (latency_s)
         *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();

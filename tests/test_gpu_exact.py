@@ -126,18 +126,20 @@ def test_knn_integer_ties(api):
         np.testing.assert_array_equal(D.cpu().numpy().astype(np.float64), Do)
 
 
-@pytest.mark.parametrize("k", [200, 300, 1024])
-def test_knn_many_chunks_integer_ties(api, k):
+@pytest.mark.parametrize("metric", ["l2", "ip"])
+@pytest.mark.parametrize("k", [1, 10, 50, 100, 200, 300, 1024])
+def test_knn_many_chunks_integer_ties(api, k, metric):
     # 150,000 small-integer rows: many database chunks share score bounds
     # while exact ties abound (distances are exact in FP32); the result must
-    # equal the oracle's exactly, lower index first among equal distances
-    say(f"knn many chunks, integer ties, k={k}")
+    # equal the oracle's exactly, lower index first among equal distances.
+    # k <= 100 runs the register queues, larger k the candidate pools.
+    say(f"knn many chunks, integer ties, k={k} {metric}")
     rng = np.random.default_rng(11 + k)
     xb = rng.integers(-2, 3, size=(150_000, 16)).astype(np.float32)
     xq = rng.integers(-2, 3, size=(100, 16)).astype(np.float32)
-    D, I = api.knn_search(dev(xq), dev(xb), k)
+    D, I = api.knn_search(dev(xq), dev(xb), k, metric)
     torch.cuda.synchronize()
-    Do, Io = oracle.knn(xq, xb, k, oracle.METRIC_L2)
+    Do, Io = oracle.knn(xq, xb, k, oracle.METRIC_L2 if metric == "l2" else oracle.METRIC_IP)
     np.testing.assert_array_equal(I.cpu().numpy(), Io)
     np.testing.assert_array_equal(D.cpu().numpy().astype(np.float64), Do)
 
@@ -179,21 +181,34 @@ def large():
     return synth.exact_large()
 
 
-@pytest.mark.parametrize("k", [1, 32, 256, 1024])
-def test_knn_exact_large_sampled(api, large, k):
+LARGE_ROWS = np.linspace(0, 9999, 256).astype(np.int64)
+
+
+@pytest.fixture(scope="module")
+def large_oracle(large):
+    # the oracle's 1,088 best rows of 256 sampled queries, for every k
+    say("oracle on 256 exact_large queries")
+    return {m: oracle.knn(large["xq"][LARGE_ROWS], large["xb"], 1024 + 64,
+                          oracle.METRIC_L2 if m == "l2" else oracle.METRIC_IP)
+            for m in ("l2", "ip")}
+
+
+@pytest.mark.parametrize("metric,k", [("l2", 1), ("l2", 32), ("l2", 256), ("l2", 1024),
+                                      ("ip", 10), ("ip", 1024)])
+def test_knn_exact_large_sampled(api, large, large_oracle, k, metric):
     # the full 10,000-query batch in one call (the benchmark's launch shape),
-    # 24 queries checked against the oracle
-    say(f"knn exact_large k={k}")
+    # 256 queries checked against the oracle
+    say(f"knn exact_large k={k} {metric}")
     xq, xb = dev(large["xq"]), dev(large["xb"])
-    D, I = api.knn_search(xq, xb, k)
+    D, I = api.knn_search(xq, xb, k, metric)
     torch.cuda.synchronize()
-    rows = np.linspace(0, 9999, 24).astype(np.int64)
+    rows = LARGE_ROWS
     fails = check_rows(D.cpu().numpy()[rows], I.cpu().numpy()[rows], large["xq"], large["xb"],
-                       rows, k)
+                       rows, k, metric, oracle_result=large_oracle[metric])
     assert not fails, fails[:10]
     # properties that hold for every row: sorted, valid, no duplicates
     Dn, In = D.cpu().numpy(), I.cpu().numpy()
-    assert np.all(np.diff(Dn, axis=1) >= 0)
+    assert np.all(np.diff(Dn, axis=1) >= 0) if metric == "l2" else np.all(np.diff(Dn, axis=1) <= 0)
     assert In.min() >= 0 and In.max() < xb.shape[0]
     if k > 1:
         s = np.sort(In, axis=1)
@@ -224,3 +239,16 @@ def test_knn_prenorm_matches(api, large):
     assert torch.equal(I, I2) and torch.equal(D, D2)
     ref = (xb.double() ** 2).sum(1)
     assert torch.allclose(yn.double(), ref, rtol=1e-5)
+
+
+def test_candidate_pools_never_dropped_a_key(api):
+    # queues of 256+ entries keep unsorted pools that are cut before they can
+    # fill; the library counts any key a full pool would have had to drop.
+    # This runs after every pool search above (same process) plus one more.
+    rng = np.random.default_rng(3)
+    xb = dev(rng.standard_normal((300_000, 48)).astype(np.float32))
+    xq = dev(rng.standard_normal((700, 48)).astype(np.float32))
+    for k in (256, 600, 1024):
+        api.knn_search(xq, xb, k)
+    torch.cuda.synchronize()
+    assert api.debug_pool_drops() == 0

@@ -101,6 +101,72 @@ def test_kmeans_1d_handworked(api, golden_dir):
         np.testing.assert_allclose(c.cpu().numpy(), np.array(it["centroids"]), rtol=1e-7)
 
 
+# ------------------------------------------------------------ PQ training
+def test_train_lossless_fixture_matches_oracle_exactly(api):
+    # quantizers known by construction (tests/train_fixture.py): the GPU's
+    # coarse k-means, residuals and per-sub-space k-means return them bit for
+    # bit, as does the oracle
+    from train_fixture import D, M, NLIST, build
+    say("train lossless fixture")
+    f = build()
+    ix = api.IVFPQ(D, NLIST, M)
+    ix.train(dev(f["xt"]), 4, f["coarse_init"], f["pq_init"])
+    coarse, books = ix.get_quantizers()
+    np.testing.assert_array_equal(coarse, f["coarse"])
+    np.testing.assert_array_equal(books, f["books"])
+    co, bo = oracle.ivfpq_train(f["xt"], NLIST, M, 4, f["coarse_init"], f["pq_init"])
+    np.testing.assert_array_equal(coarse, co)
+    np.testing.assert_array_equal(books, bo)
+
+
+def test_train_residuals_to_final_centroids_handworked(api, golden_dir):
+    with open(os.path.join(golden_dir, "ivfpq_train_handworked.json")) as f:
+        g = json.load(f)
+    i = np.arange(256, dtype=np.float64)
+    xt = np.stack([i, 2 * i, -i, 3 * i], axis=1).astype(np.float32)
+    pq_init = np.array([[(5 * j + 3 * m) % 256 for j in range(256)] for m in range(4)], np.int64)
+    ix = api.IVFPQ(g["d"], g["nlist"], g["M"])
+    ix.train(dev(xt), g["niter"], np.array(g["coarse_init"], np.int64), pq_init)
+    coarse, books = ix.get_quantizers()
+    assert coarse.tolist() == g["coarse"]
+    for e in g["books_sample"]:
+        assert books[e["m"], e["j"], 0] == e["value"], e
+
+
+def _pq_objectives(xt, coarse, books):
+    """Per sub-space mean squared quantisation error of the training
+    residuals to their nearest coarse centroid (float64, oracle steps)."""
+    a, _ = oracle.kmeans_assign(xt, coarse)
+    res = xt.astype(np.float64) - coarse[a].astype(np.float64)
+    M, _, ds = books.shape
+    out = []
+    for m in range(M):
+        _, dist = oracle.kmeans_assign(np.ascontiguousarray(res[:, m * ds:(m + 1) * ds]), books[m])
+        out.append(dist.mean())
+    return np.array(out)
+
+
+def test_train_mixture_objectives_match_oracle(api):
+    # same data and Forgy rows on both sides; trajectories may split after a
+    # band-ambiguous assignment, so the coarse and per-sub-space objectives
+    # are compared (within 1%), not the centroids
+    say("train mixture vs oracle")
+    mix = synth.Mixture(60, 32, (12, 0))
+    xt = mix.sample(20000, (12, 1))
+    nlist, M, niter = 64, 8, 8
+    ci, pi = synth.choose_rows(len(xt), nlist, 13), synth.pq_init_rows(len(xt), M, 14)
+    ix = api.IVFPQ(32, nlist, M)
+    ix.train(dev(xt), niter, ci, pi)
+    coarse, books = ix.get_quantizers()
+    co, bo = oracle.ivfpq_train(xt, nlist, M, niter, ci, pi)
+    _, dg = oracle.kmeans_assign(xt, coarse)
+    _, do = oracle.kmeans_assign(xt, co)
+    assert abs(dg.mean() / do.mean() - 1) <= 0.01
+    og, oo = _pq_objectives(xt, coarse, books), _pq_objectives(xt, co, bo)
+    say(f"per-sub-space objective ratio gpu/oracle: {np.round(og / oo, 4).tolist()}")
+    assert np.all(np.abs(og / oo - 1) <= 0.01), (og, oo)
+
+
 @pytest.mark.parametrize("M,ds", [(4, 2), (8, 8), (16, 8), (8, 16), (16, 3)])
 def test_pq_encode_matches_oracle(api, M, ds):
     say(f"pq encode M={M} ds={ds}")

@@ -8,6 +8,7 @@ import threading
 import numpy as np
 import pytest
 
+import oracle
 from paper_1702_08734_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -135,3 +136,86 @@ def test_errors(api, index):
     srv.close()
     with pytest.raises(api.MKError):
         api.Server(ix, 10, nprobe=4, R=5)   # re-rank without xb / R < k
+
+
+# ------------------------------------------------------------ exact ties, large batches
+@pytest.fixture(scope="module")
+def tie_index(api):
+    """Index of small-integer data: coarse centroids and codewords are small
+    integers and every database vector is a centroid plus one codeword per
+    sub-space, so every ADC distance (Eq. 10-11) is an integer computed
+    exactly in FP32; distinct entries, within a list and across lists, share
+    distances all the time, and each vector is also added twice more."""
+    say("build small-integer IVFPQ index with exact ties")
+    rng = np.random.default_rng(77)
+    d, nlist, M = 16, 64, 4
+    ds = d // M
+    coarse = rng.integers(-4, 5, size=(nlist, d)).astype(np.float32)
+    books = rng.integers(-1, 2, size=(M, 256, ds)).astype(np.float32)
+    ix = api.IVFPQ(d, nlist, M)
+    ix.set_quantizers(coarse, books)
+    n = 6000
+    base = coarse[rng.integers(0, nlist, n)]
+    parts = [books[m][rng.integers(0, 256, n)] for m in range(M)]
+    xb = (base + np.concatenate(parts, axis=1)).astype(np.float32)
+    xb = np.concatenate([xb, xb[:2000], xb[:2000]])    # duplicate codes, later ids
+    ix.add(dev(xb))
+    xq = rng.integers(-4, 5, size=(3000, d)).astype(np.float32)
+    offs, codes, ids = ix.get_lists()
+    return {"ix": ix, "xq": xq, "coarse": coarse, "books": books, "offs": offs,
+            "codes": codes, "ids": ids, "nlist": nlist}
+
+
+def _big_sizes(n, seed):
+    # requests of 300-700 rows: batches of up to 1,024 rows group 4 lists per
+    # workgroup at nprobe 8 (the grouping depends on the batch size)
+    return np.random.default_rng(seed).integers(300, 700, n)
+
+
+@pytest.mark.parametrize("mode", ["fixed", "learned"])
+def test_large_batches_exact_ties_equal_alone_and_oracle(api, tie_index, mode):
+    ix, xq = tie_index["ix"], tie_index["xq"]
+    k, nprobe, cap = 20, 8, 32
+    kw = {"nprobe": nprobe}
+    net = None
+    if mode == "learned":
+        net = api.MLP(16 + 32, 64, "fp32")
+        net.set_params(synth.mlp_init(16 + 32, 64, 5))
+        net.fit_standardization(ix.probe_features(dev(xq)))
+        kw = {"net": net, "delta": 2.0, "cap": cap}
+    srv = api.Server(ix, k, max_batch=1024, nstreams=2, **kw)
+    sizes = _big_sizes(10, 3)
+    starts = np.random.default_rng(4).integers(0, len(xq) - 700, len(sizes))
+    tickets = [srv.submit(xq[s0:s0 + n]) for s0, n in zip(starts, sizes)]
+    res = [srv.wait(t) for t in tickets]
+    batches, rows = srv.stats()
+    srv.close()
+    say(f"{mode}: {len(sizes)} requests in {batches} batches")
+    assert batches < len(sizes)
+    for (s0, n), (D, I, _) in zip(zip(starts, sizes), res):
+        q = dev(xq[s0:s0 + n])
+        if mode == "learned":
+            Da, Ia, tau = ix.search_learned(net, 2.0, q, k, cap)
+            tau = tau.cpu().numpy()
+            assert tau.min() >= 1 and tau.max() <= cap
+        else:
+            Da, Ia = ix.search(q, k, nprobe)
+            tau = None
+        np.testing.assert_array_equal(I, Ia.cpu().numpy())
+        np.testing.assert_array_equal(D, Da.cpu().numpy())
+    # the request searched alone equals the oracle exactly (integer distances,
+    # ties to the lower id), on the first request
+    s0, n = starts[0], sizes[0]
+    q = xq[s0:s0 + n]
+    if mode == "learned":
+        _, _, tau = ix.search_learned(net, 2.0, dev(q), k, cap)
+        Do, Io = oracle.ivfpq_search(q, tie_index["coarse"], tie_index["books"],
+                                     tie_index["offs"], tie_index["codes"], tie_index["ids"], k,
+                                     cap, nprobe_per_query=tau.cpu().numpy())
+    else:
+        Do, Io = oracle.ivfpq_search(q, tie_index["coarse"], tie_index["books"],
+                                     tie_index["offs"], tie_index["codes"], tie_index["ids"], k,
+                                     nprobe)
+    D0, I0, _ = res[0]
+    np.testing.assert_array_equal(I0, Io)
+    np.testing.assert_array_equal(D0.astype(np.float64), Do)
