@@ -55,13 +55,15 @@ def _load():
     lib.oracle_set_threads.restype = None
     lib.oracle_get_threads.argtypes = []
     lib.oracle_get_threads.restype = ctypes.c_int
-    lib.oracle_knn.argtypes = [_f32p, _i64, _f32p, _i64, _i32, _i32, _i32, _f64p, _i64p]
+    lib.oracle_knn.argtypes = [_f32p, _i64, _f32p, _i64, _i32, _i32, _i32, ctypes.c_void_p,
+                               _f64p, _i64p]
     lib.oracle_kselect.argtypes = [_f32p, _i64, _i64, _i32, _i32, _f64p, _i64p]
     lib.oracle_kmeans_assign.argtypes = [_f64p, _i64, _i32, _f32p, _i32, _i64p, _f64p]
     lib.oracle_kmeans_update.argtypes = [_f64p, _i64, _i32, _i64p, _i32, _f32p, _i64p]
     lib.oracle_pq_encode.argtypes = [_f64p, _i64, _i32, _i32, _f32p, _u8p]
     lib.oracle_ivfpq_search.argtypes = [_f32p, _i64, _i32, _f32p, _i32, _i32, _f32p, _i64p,
-                                        _u8p, _i64p, _i32, _i32, ctypes.c_void_p, _f64p, _i64p]
+                                        _u8p, _i64p, _i32, _i32, ctypes.c_void_p, ctypes.c_void_p,
+                                        _f64p, _i64p]
     for fn in ("oracle_knn", "oracle_kselect", "oracle_kmeans_assign", "oracle_kmeans_update",
                "oracle_pq_encode", "oracle_ivfpq_search"):
         getattr(lib, fn).restype = ctypes.c_int
@@ -93,11 +95,20 @@ def _f64(a) -> np.ndarray:
 # --------------------------------------------------------------------------
 # Exact search and k-selection (Section 2, Eq. 1; Section 4 contract)
 # --------------------------------------------------------------------------
-def knn(xq, xb, k: int, metric: int = METRIC_L2):
+def _opt_i64(a):
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, np.int64)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def knn(xq, xb, k: int, metric: int = METRIC_L2, exclude=None):
     """Exact k-NN by full sort in float64 (Section 2, Eq. 1).
 
     Returns (D float64 [nq, k], I int64 [nq, k]); squared L2 ascending or
     inner product descending, ties to the lower index, padded (+-inf, -1).
+    exclude [nq] (optional): a database row left out of each query's
+    candidates (the node itself when building a k-NN graph, Section 6.5).
     """
     xq = _f32(xq)
     xb = _f32(xb)
@@ -107,8 +118,10 @@ def knn(xq, xb, k: int, metric: int = METRIC_L2):
         assert xb.shape[1] == d
     D = np.empty((nq, k), np.float64)
     I = np.empty((nq, k), np.int64)
+    ex, exp = _opt_i64(exclude)
+    assert ex is None or ex.shape == (nq,)
     _check(_load().oracle_knn(xq, nq, xb if nb else np.zeros((1, d), np.float32), nb, d, k,
-                              metric, D, I), "knn")
+                              metric, exp, D, I), "knn")
     return D, I
 
 
@@ -242,8 +255,11 @@ def build_lists(list_of, codes, nlist: int, id0: int = 0, prev=None):
 
 
 def ivfpq_search(xq, coarse, codebooks, offsets, codes, ids, k: int, nprobe: int,
-                 nprobe_per_query=None):
-    """IVFADC search, Algorithm 4 with Eq. 5, 6 and 10 (float64, full sort)."""
+                 nprobe_per_query=None, exclude=None):
+    """IVFADC search, Algorithm 4 with Eq. 5, 6 and 10 (float64, full sort).
+
+    exclude [nq] (optional): an id whose entries are skipped for each query.
+    """
     xq = _f32(xq)
     coarse = _f32(coarse)
     cb = _f32(codebooks)
@@ -260,25 +276,30 @@ def ivfpq_search(xq, coarse, codebooks, offsets, codes, ids, k: int, nprobe: int
     ids_a = np.ascontiguousarray(ids, np.int64)
     if ids_a.size == 0:
         ids_a = np.zeros(1, np.int64)
+    ex, exp = _opt_i64(exclude)
+    assert ex is None or ex.shape == (nq,)
     _check(_load().oracle_ivfpq_search(
         xq, nq, d, coarse, coarse.shape[0], M, cb, np.ascontiguousarray(offsets, np.int64),
         codes, ids_a, k, nprobe,
-        npq.ctypes.data_as(ctypes.c_void_p) if npq is not None else None, D, I), "ivfpq_search")
+        npq.ctypes.data_as(ctypes.c_void_p) if npq is not None else None, exp, D, I),
+        "ivfpq_search")
     return D, I
 
 
 def ivfpq_search_rerank(xq, coarse, codebooks, offsets, codes, ids, xb, k: int, nprobe: int,
-                        R: int):
+                        R: int, exclude=None):
     """IVFADC short list re-ranked exactly (an extension of Algorithm 4).
 
     The R best entries by ADC distance (``ivfpq_search`` with k = R) are
     re-scored by their exact squared L2 distance to the database row of their
     id (float64 direct form) and the first k by (distance, id) are returned,
     padded with (+inf, -1) where fewer than k entries were scanned.
+    exclude [nq] (optional): an id left out of each query's short list.
     """
     xq = _f32(xq)
     xb = _f32(xb)
-    _, Ia = ivfpq_search(xq, coarse, codebooks, offsets, codes, ids, R, nprobe)
+    _, Ia = ivfpq_search(xq, coarse, codebooks, offsets, codes, ids, R, nprobe,
+                         exclude=exclude)
     nq = xq.shape[0]
     D = np.full((nq, k), np.inf)
     I = np.full((nq, k), -1, np.int64)

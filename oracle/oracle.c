@@ -112,9 +112,13 @@ static double dot_f32(const float* x, const float* y, int32_t d) {
  * returned.  Squared L2 is reported (the distance matrix D of Section 2 holds
  * squared distances; the argmin of Eq. 1 is the same).  Missing entries when
  * nb < k are (+inf, -1) for L2 and (-inf, -1) for inner product.
+ * exclude, if non-NULL, names one database row per query that is left out of
+ * that query's candidates (a node of a k-NN graph is not its own neighbour,
+ * Section 6.5).
  */
 int oracle_knn(const float* xq, int64_t nq, const float* xb, int64_t nb,
-               int32_t d, int32_t k, int32_t metric, double* D, int64_t* I) {
+               int32_t d, int32_t k, int32_t metric, const int64_t* exclude,
+               double* D, int64_t* I) {
     if (nq < 0 || nb < 0 || d < 1 || k < 1) return -1;
     if (metric != OR_L2 && metric != OR_IP) return -1;
     int fail = 0;
@@ -129,13 +133,17 @@ int oracle_knn(const float* xq, int64_t nq, const float* xb, int64_t nb,
         for (int64_t j = 0; j < nq; j++) {
             if (!p) continue;
             const float* x = xq + j * (int64_t)d;
+            const int64_t skip = exclude ? exclude[j] : -1;
+            int64_t n = 0;
             for (int64_t i = 0; i < nb; i++) {
+                if (i == skip) continue;
                 const float* y = xb + i * (int64_t)d;
-                p[i].v = metric == OR_L2 ? l2sq_f32(x, y, d) : dot_f32(x, y, d);
-                p[i].i = i;
+                p[n].v = metric == OR_L2 ? l2sq_f32(x, y, d) : dot_f32(x, y, d);
+                p[n].i = i;
+                n++;
             }
-            qsort(p, (size_t)nb, sizeof(pair_t), metric == OR_L2 ? cmp_asc : cmp_desc);
-            emit_topk(p, nb, k, metric == OR_IP, D + j * (int64_t)k, I + j * (int64_t)k);
+            qsort(p, (size_t)n, sizeof(pair_t), metric == OR_L2 ? cmp_asc : cmp_desc);
+            emit_topk(p, n, k, metric == OR_IP, D + j * (int64_t)k, I + j * (int64_t)k);
         }
         free(p);
     }
@@ -304,7 +312,9 @@ int oracle_pq_encode(const double* r, int64_t n, int32_t d, int32_t M,
  *   3. all (distance, id) pairs are sorted, ties to the lower id, and the
  *      first k are returned, padded with (+inf, -1)  -- Eq. 6.
  * nprobe_per_query, if non-NULL, gives each query its own nprobe and
- * overrides nprobe.
+ * overrides nprobe.  exclude, if non-NULL, names one id per query whose
+ * entries are skipped (the query's own node when a k-NN graph is built by
+ * searching the database against itself, Section 6.5).
  * Lists are in CSR form: entries list_offsets[L] .. list_offsets[L+1]-1 of
  * codes ([ntotal][M] bytes) and ids belong to list L.
  */
@@ -313,7 +323,7 @@ int oracle_ivfpq_search(const float* xq, int64_t nq, int32_t d,
                         const float* codebooks, const int64_t* list_offsets,
                         const uint8_t* codes, const int64_t* ids, int32_t k,
                         int32_t nprobe, const int32_t* nprobe_per_query,
-                        double* D, int64_t* I) {
+                        const int64_t* exclude, double* D, int64_t* I) {
     if (nq < 0 || d < 1 || nlist < 1 || M < 1 || d % M != 0 || k < 1) return -1;
     int32_t ds = d / M;
     int64_t ntotal = list_offsets[nlist];
@@ -345,6 +355,7 @@ int oracle_ivfpq_search(const float* xq, int64_t nq, int32_t d,
                 const float* cL = coarse + L * d;
                 for (int32_t t = 0; t < d; t++) res[t] = (double)x[t] - (double)cL[t];
                 for (int64_t e = list_offsets[L]; e < list_offsets[L + 1]; e++) {
+                    if (exclude && ids[e] == exclude[j]) continue;
                     double s = 0.0;
                     for (int32_t m = 0; m < M; m++) {
                         const float* cw = codebooks + ((int64_t)m * 256 + codes[e * M + m]) * ds;

@@ -458,3 +458,81 @@ def test_kmeans_loop_1d_handworked(golden_dir):
     # objectives are measured against FP32-rounded centroids (7.3333335)
     np.testing.assert_allclose(objs, [it["objective"] for it in g["iterations"]], rtol=1e-6)
     np.testing.assert_allclose(c, np.array(g["iterations"][-1]["centroids"]), rtol=1e-7)
+
+
+# ------------------------------------------------------------ k-NN graph
+def test_knn_graph_exact_bruteforce_with_ties():
+    # Section 6.5: every node queried against the whole set, the node itself
+    # left out.  Pure-Python double loop on small-integer points with many
+    # equal distances and duplicate points (a duplicate is a neighbour at 0).
+    rng = np.random.default_rng(61)
+    x = rng.integers(-2, 3, size=(40, 3)).astype(np.float32)
+    x[7] = x[3]
+    k = 6
+    D, I = oracle.knn(x, x, k, exclude=np.arange(len(x)))
+    for i in range(len(x)):
+        cand = []
+        for j in range(len(x)):
+            if j == i:
+                continue
+            cand.append((sum((float(x[i, t]) - float(x[j, t])) ** 2 for t in range(3)), j))
+        cand.sort()
+        assert I[i].tolist() == [j for _, j in cand[:k]]
+        assert D[i].tolist() == [v for v, _ in cand[:k]]
+        assert i not in I[i]
+    assert I[3, 0] == 7 and D[3, 0] == 0.0 and I[7, 0] == 3
+    # nb - 1 candidates only: the last slot is padding
+    D, I = oracle.knn(x[:5], x[:5], 5, exclude=np.arange(5))
+    assert np.all(I[:, 4] == -1) and np.all(np.isinf(D[:, 4]))
+
+
+def test_knn_graph_exclude_is_per_query():
+    # excluding another row than the query's own removes exactly that row
+    rng = np.random.default_rng(62)
+    xb = rng.standard_normal((50, 4)).astype(np.float32)
+    xq = rng.standard_normal((5, 4)).astype(np.float32)
+    D0, I0 = oracle.knn(xq, xb, 10)
+    ex = I0[:, 0].copy()
+    D1, I1 = oracle.knn(xq, xb, 9, exclude=ex)
+    np.testing.assert_array_equal(I1, I0[:, 1:])
+    np.testing.assert_array_equal(D1, D0[:, 1:])
+    # an id outside the database excludes nothing
+    D2, I2 = oracle.knn(xq, xb, 10, exclude=np.full(5, -1))
+    np.testing.assert_array_equal(I2, I0)
+
+
+def test_ivfpq_graph_lossless_equals_exact_graph():
+    # a database made exactly of coarse centroid + codewords, every list
+    # probed: the IVFADC graph equals the exact graph (self left out on both)
+    rng = np.random.default_rng(63)
+    M, ds, nlist = 2, 2, 3
+    d = M * ds
+    coarse = rng.integers(-20, 20, size=(nlist, d)).astype(np.float32) * 4
+    books = rng.integers(-1, 2, size=(M, 256, ds)).astype(np.float32)
+    books[:, :9] = np.array([[a, b] for a in (-1, 0, 1) for b in (-1, 0, 1)], np.float32)
+    books[:, 9:] = 50.0
+    L = rng.integers(0, nlist, 80)
+    cw = rng.integers(0, 9, size=(80, M))
+    xb = (coarse[L] + np.concatenate([books[m][cw[:, m]] for m in range(M)], 1)).astype(np.float32)
+    lists, codes = oracle.ivf_encode(xb, coarse, books)
+    offs, lc, lid = oracle.build_lists(lists, codes, nlist)
+    self_ids = np.arange(len(xb))
+    D, I = oracle.ivfpq_search(xb, coarse, books, offs, lc, lid, 10, nlist, exclude=self_ids)
+    De, Ie = oracle.knn(xb, xb, 10, exclude=self_ids)
+    np.testing.assert_array_equal(I, Ie)
+    np.testing.assert_array_equal(D, De)
+    assert not np.any(I == self_ids[:, None])
+
+
+def test_ivfpq_graph_drops_only_the_node():
+    # with the node excluded, the result is the unexcluded search of k + 1
+    # with the node's entry removed (wherever it ranked), else its first k
+    xq, xb, coarse, books, lists, codes, offs, lc, lid = _random_index(64)
+    nodes = np.array([0, 5, 17, 120, 299])
+    k = 8
+    Da, Ia = oracle.ivfpq_search(xb[nodes], coarse, books, offs, lc, lid, k + 1, 2)
+    D, I = oracle.ivfpq_search(xb[nodes], coarse, books, offs, lc, lid, k, 2, exclude=nodes)
+    for j, n in enumerate(nodes):
+        keep = Ia[j] != n
+        np.testing.assert_array_equal(I[j], Ia[j][keep][:k])
+        np.testing.assert_array_equal(D[j], Da[j][keep][:k])
