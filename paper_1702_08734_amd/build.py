@@ -57,13 +57,30 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    """Compile all sources and link the shared library; returns its path."""
+def _stale(src: str, newest_header: float) -> bool:
+    obj = os.path.join(OBJDIR, os.path.basename(src)[:-4] + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return t < os.path.getmtime(src) or t < newest_header
+
+
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile all sources and link the shared library; returns its path.
+    With incremental=True only sources older than their object, or than any
+    header, are recompiled."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sources()
-    jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
+    todo = srcs
+    if incremental:
+        headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+        headers += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE)]
+        newest = max(os.path.getmtime(h) for h in headers)
+        todo = [s for s in srcs if _stale(s, newest)]
+    jobs = jobs or min(max(len(todo), 1), max(1, min(8, os.cpu_count() or 1)))
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(OBJDIR, os.path.basename(s)[:-4] + ".o") for s in srcs]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -76,5 +93,5 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)
