@@ -108,6 +108,21 @@ mk_status mk_knn_search_prenorm(const float* xq, int64_t nq, const float* xb, co
                                 int64_t* I, mk_stream_t stream);
 
 /*
+ * Rows node0 .. node0 + nnodes - 1 of the exact k-nearest-neighbour graph of
+ * the database (Section 6.5: every vector searched against the whole
+ * database): for each node i the k best rows j != i by the metric of
+ * mk_knn_search (squared L2 ascending or inner product descending, ties to the
+ * lower row), the node itself left out.  Computed as the k + 1 best, with the
+ * node removed from them if present.
+ *   xb [nb, d] float32 (nodes are its rows), D [nnodes, k] float32,
+ *   I [nnodes, k] int64 (padded (+-inf, -1) when nb - 1 < k).
+ * 1 <= k <= 1023 (one entry of the 1024-entry selector goes to the node).
+ * Scratch: nnodes (k + 1) 12 bytes plus that of mk_knn_search with k + 1.
+ */
+mk_status mk_knn_graph(const float* xb, int64_t nb, int32_t d, int32_t k, mk_metric metric,
+                       int64_t node0, int64_t nnodes, float* D, int64_t* I, mk_stream_t stream);
+
+/*
  * k-means assignment step (Section 6.2: exact search with k = 1): for each
  * point the nearest centroid (squared L2, ties to the lower index) and that
  * squared distance (direct form, FP32).
@@ -230,6 +245,20 @@ int64_t mk_ivfpq_ntotal(const mk_ivfpq* index);
  */
 mk_status mk_ivfpq_search(mk_ivfpq* index, const float* xq, int64_t nq, int32_t k,
                           int32_t nprobe, float* D, int64_t* I, mk_stream_t stream);
+
+/*
+ * Rows node0 .. node0 + nnodes - 1 of the approximate k-NN graph of the
+ * indexed vectors (Section 6.5): each added vector with id i (row i of xb,
+ * the array that was added, ids 0 .. ntotal - 1) is searched against the
+ * index as by mk_ivfpq_search, and entries with id i are skipped, so a node
+ * is never its own neighbour.  Nodes are processed in batches of 32768
+ * queries on `stream`.
+ *   xb [ntotal, d] float32, D [nnodes, k] float32 (ADC distances),
+ *   I [nnodes, k] int64.  node0 + nnodes <= ntotal.
+ */
+mk_status mk_ivfpq_knn_graph(mk_ivfpq* index, const float* xb, int64_t node0, int64_t nnodes,
+                             int32_t k, int32_t nprobe, float* D, int64_t* I,
+                             mk_stream_t stream);
 
 /*
  * IVFADC search as above for a short list of the R best entries by ADC

@@ -40,6 +40,8 @@ _SIGS = {
     "mk_norms": [_vp, _i64, _i32, _vp, _vp],
     "mk_kselect": [_vp, _i64, _i64, _i32, _i32, _vp, _vp, _vp],
     "mk_knn_search": [_vp, _i64, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
+    "mk_knn_graph": [_vp, _i64, _i32, _i32, _i32, _i64, _i64, _vp, _vp, _vp],
+    "mk_ivfpq_knn_graph": [_vp, _vp, _i64, _i64, _i32, _i32, _vp, _vp, _vp],
     "mk_knn_search_prenorm": [_vp, _i64, _vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
     "mk_kmeans_assign": [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp],
     "mk_kmeans_update": [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp],
@@ -175,6 +177,20 @@ def knn_search(xq: torch.Tensor, xb: torch.Tensor, k: int, metric: str = "l2",
     return D, I
 
 
+def knn_graph(xb: torch.Tensor, k: int, metric: str = "l2", node0: int = 0,
+              nnodes: int | None = None):
+    """Rows node0 .. node0 + nnodes - 1 of the exact k-NN graph of xb (a node
+    is not its own neighbour): (D [nnodes, k], I [nnodes, k])."""
+    _dev(xb, torch.float32, "xb")
+    nb, d = xb.shape
+    nnodes = nb - node0 if nnodes is None else nnodes
+    D = _out((nnodes, k), torch.float32, xb)
+    I = _out((nnodes, k), torch.int64, xb)
+    _call("mk_knn_graph", _ptr(xb), nb, d, k, METRICS[metric], node0, nnodes, _ptr(D), _ptr(I),
+          _stream())
+    return D, I
+
+
 def quantize_rows(x: torch.Tensor, prec: str):
     """Low-precision copy of the rows of x: (uint8 tensor [n, ld * bytes],
     float32 1/scale per row)."""
@@ -279,6 +295,20 @@ class IVFPQ:
         D = _out((nq, k), torch.float32, xq)
         I = _out((nq, k), torch.int64, xq)
         _call("mk_ivfpq_search", self._h, _ptr(xq), nq, k, nprobe, _ptr(D), _ptr(I), _stream())
+        return D, I
+
+    def knn_graph(self, xb: torch.Tensor, k: int, nprobe: int, node0: int = 0,
+                  nnodes: int | None = None):
+        """Rows node0 .. node0 + nnodes - 1 of the IVFADC k-NN graph of the
+        added vectors xb (ids 0 .. ntotal - 1); a node is not its own neighbour."""
+        _dev(xb, torch.float32, "xb")
+        if xb.dim() != 2 or xb.shape[1] != self.d or xb.shape[0] < self.ntotal:
+            raise ValueError(f"xb must be the [ntotal, {self.d}] added vectors")
+        nnodes = self.ntotal - node0 if nnodes is None else nnodes
+        D = _out((nnodes, k), torch.float32, xb)
+        I = _out((nnodes, k), torch.int64, xb)
+        _call("mk_ivfpq_knn_graph", self._h, _ptr(xb), node0, nnodes, k, nprobe, _ptr(D),
+              _ptr(I), _stream())
         return D, I
 
     def search_rerank(self, xq: torch.Tensor, k: int, nprobe: int, R: int, xb: torch.Tensor):

@@ -520,7 +520,7 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
     const int64_t* __restrict__ offsets, const uint8_t* __restrict__ codes,
     const int64_t* __restrict__ ids, int32_t M, int32_t G, int32_t k,
     uint64_t* __restrict__ part, const int64_t* __restrict__ work,
-    const int32_t* __restrict__ tau, int64_t nq) {
+    const int32_t* __restrict__ tau, int64_t nq, int64_t excl_base) {
     constexpr int T = SelParams<KR>::T;
     extern __shared__ __align__(16) unsigned char smem[];
     float* lut = reinterpret_cast<float*>(smem);
@@ -550,6 +550,9 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
     uint64_t* out = part + item * k;
+    // k-NN graph construction: query q is node excl_base + q, not its own
+    // neighbour (no exclusion when excl_base < 0; ids are >= 0)
+    const int64_t excl = excl_base >= 0 ? excl_base + q : -1;
 
     const float* t3 = term3 + q * (int64_t)M * 256;
     for (int e = threadIdx.x; e < M * 256; e += 64 * kScanWaves) lut[e] = -2.f * t3[e];
@@ -603,7 +606,10 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
             // the selected set does not depend on how lists are grouped; the
             // id is read only for an entry that can enter the queue
             uint64_t key = kSentinel;
-            if (ok && ws.may_take(dist)) key = make_key(dist, (uint32_t)lid[e]);
+            if (ok && ws.may_take(dist)) {
+                const int64_t id = lid[e];
+                if (id != excl) key = make_key(dist, (uint32_t)id);
+            }
             if (ws.push(key)) ws.merge();
         }
     }
@@ -645,7 +651,8 @@ mk_status launch_scan(const float* term3, const float* t1e, const float* cd, con
                       int32_t ld, const int64_t* offsets, const uint8_t* codes,
                       const int64_t* ids, int32_t M, int64_t nq, int32_t G, int32_t k,
                       uint64_t* part, int64_t items, hipStream_t s,
-                      const int64_t* work = nullptr, const int32_t* tau = nullptr) {
+                      const int64_t* work = nullptr, const int32_t* tau = nullptr,
+                      int64_t excl_base = -1) {
     if (items == 0) return MK_OK;
     MK_REQUIRE(items < (1ll << 31), MK_ERR_UNSUPPORTED, "too many scan items for one launch");
     const size_t shm = (size_t)M * 256 * sizeof(float) + (size_t)kScanWaves * k * sizeof(uint64_t);
@@ -655,7 +662,7 @@ mk_status launch_scan(const float* term3, const float* t1e, const float* cd, con
     ProfScope prof("ivf_scan", s);
 #define MK_SCAN(KR)                                                                          \
     hipLaunchKernelGGL(ivf_scan<KR>, grid, block, shm, s, term3, t1e, cd, ci, ld, offsets,  \
-                       codes, ids, M, G, k, part, work, tau, nq)
+                       codes, ids, M, G, k, part, work, tau, nq, excl_base)
     switch (queue_regs(k)) {
         case 1: MK_SCAN(1); break;
         case 2: MK_SCAN(2); break;
@@ -837,7 +844,7 @@ mk_status add(mk_ivfpq* ix, const float* xb, int64_t nb, hipStream_t s) {
 // search over the coarse centroids (Eq. 5), term 3 per query, and the list
 // scan into `part` = per query `ngroups` partial lists of kk keys.
 mk_status scan_fixed(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t nprobe, int32_t kk,
-                     Scratch& part, int64_t* ngroups, hipStream_t s) {
+                     Scratch& part, int64_t* ngroups, hipStream_t s, int64_t excl_base = -1) {
     const int32_t M = ix->M;
     Scratch cd, ci, t3;
     MK_TRY(cd.alloc(sizeof(float) * nq * nprobe, s));
@@ -854,14 +861,14 @@ mk_status scan_fixed(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t nprobe, 
     }
     return launch_scan(t3.as<float>(), ix->t1e, cd.as<float>(), ci.as<int64_t>(), nprobe,
                        ix->offsets_dev, ix->codes, ix->ids, M, nq, G, kk, part.as<uint64_t>(),
-                       nq * *ngroups, s);
+                       nq * *ngroups, s, nullptr, nullptr, excl_base);
 }
 
 mk_status search(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t k, int32_t nprobe, float* D,
-                 int64_t* I, hipStream_t s) {
+                 int64_t* I, hipStream_t s, int64_t excl_base = -1) {
     Scratch part;
     int64_t ng = 0;
-    MK_TRY(scan_fixed(ix, xq, nq, nprobe, k, part, &ng, s));
+    MK_TRY(scan_fixed(ix, xq, nq, nprobe, k, part, &ng, s, excl_base));
     ProfScope prof("ivf_merge", s);
     return merge_key_lists(part.as<uint64_t>(), nq, (int32_t)ng, k, D, I, s);
 }
@@ -1089,6 +1096,30 @@ extern "C" mk_status mk_ivfpq_search(mk_ivfpq* ix, const float* xq, int64_t nq, 
     if (nq == 0) return MK_OK;
     MK_REQUIRE(xq && D && I, MK_ERR_INVALID_ARG, "null pointer");
     return mk::search(ix, xq, nq, k, nprobe, D, I, static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_ivfpq_knn_graph(mk_ivfpq* ix, const float* xb, int64_t node0,
+                                        int64_t nnodes, int32_t k, int32_t nprobe, float* D,
+                                        int64_t* I, mk_stream_t stream) {
+    MK_REQUIRE(ix, MK_ERR_INVALID_ARG, "null index");
+    MK_REQUIRE(ix->trained, MK_ERR_STATE, "index is not trained");
+    MK_REQUIRE(node0 >= 0 && nnodes >= 0 && node0 + nnodes <= ix->ntotal, MK_ERR_INVALID_ARG,
+               "nodes node0 .. node0 + nnodes - 1 must be ids of added vectors");
+    MK_REQUIRE(k >= 1, MK_ERR_INVALID_ARG, "k must be >= 1");
+    MK_REQUIRE(k <= mk::kMaxK, MK_ERR_UNSUPPORTED, "k must be <= 1024");
+    MK_REQUIRE(nprobe >= 1 && nprobe <= ix->nlist && nprobe <= mk::kMaxK, MK_ERR_INVALID_ARG,
+               "need 1 <= nprobe <= min(nlist, 1024)");
+    if (nnodes == 0) return MK_OK;
+    MK_REQUIRE(xb && D && I, MK_ERR_INVALID_ARG, "null pointer");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    // batches bound the scratch (coarse results, term 3, partial lists)
+    constexpr int64_t kBatch = 32768;
+    for (int64_t b = 0; b < nnodes; b += kBatch) {
+        const int64_t n = nnodes - b < kBatch ? nnodes - b : kBatch;
+        const int64_t first = node0 + b;
+        MK_TRY(mk::search(ix, xb + first * ix->d, n, k, nprobe, D + b * k, I + b * k, s, first));
+    }
+    return MK_OK;
 }
 
 extern "C" mk_status mk_ivfpq_search_rerank(mk_ivfpq* ix, const float* xq, int64_t nq,

@@ -132,6 +132,25 @@ mk_status pool_drop_counter(unsigned long long** out) {
 }
 
 
+// k-NN graph rows: the k + 1 best of node q minus the node itself (if it is
+// among them), first k kept.  One thread per node.
+__global__ void drop_node_kernel(const float* __restrict__ D1, const int64_t* __restrict__ I1,
+                                 int64_t n, int32_t k, int64_t node0, float* __restrict__ D,
+                                 int64_t* __restrict__ I) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const int64_t self = node0 + q;
+    const float* d1 = D1 + q * (k + 1);
+    const int64_t* i1 = I1 + q * (k + 1);
+    int32_t o = 0;
+    for (int32_t j = 0; j <= k && o < k; ++j) {
+        if (i1[j] == self) continue;
+        D[q * k + o] = d1[j];
+        I[q * k + o] = i1[j];
+        ++o;
+    }
+}
+
 template <int KR>
 mk_status rerank_launch(const uint64_t* keys, int64_t nq, int32_t R, const float* xq,
                         const float* xb, int32_t d, bool l2, bool vec, int32_t k, float* D,
@@ -186,6 +205,27 @@ extern "C" mk_status mk_knn_search_prenorm(const float* xq, int64_t nq, const fl
                "L2 search needs the database norms");
     return mk::knn_search(xq, nq, xb, yn, nb, d, k, metric, D, I,
                           static_cast<hipStream_t>(stream));
+}
+
+extern "C" mk_status mk_knn_graph(const float* xb, int64_t nb, int32_t d, int32_t k,
+                                  mk_metric metric, int64_t node0, int64_t nnodes, float* D,
+                                  int64_t* I, mk_stream_t stream) {
+    MK_REQUIRE(nb >= 0 && node0 >= 0 && nnodes >= 0 && node0 + nnodes <= nb, MK_ERR_INVALID_ARG,
+               "nodes node0 .. node0 + nnodes - 1 must be rows of xb");
+    MK_REQUIRE(k >= 1, MK_ERR_INVALID_ARG, "k must be >= 1");
+    MK_REQUIRE(k < mk::kMaxK, MK_ERR_UNSUPPORTED, "k must be <= 1023");
+    if (nnodes == 0) return MK_OK;
+    MK_REQUIRE(xb && D && I, MK_ERR_INVALID_ARG, "null pointer");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    mk::Scratch D1, I1;
+    MK_TRY(D1.alloc(sizeof(float) * (size_t)nnodes * (k + 1), s));
+    MK_TRY(I1.alloc(sizeof(int64_t) * (size_t)nnodes * (k + 1), s));
+    MK_TRY(mk::knn_search(xb + node0 * d, nnodes, xb, nullptr, nb, d, k + 1, metric,
+                          D1.as<float>(), I1.as<int64_t>(), s));
+    hipLaunchKernelGGL(mk::drop_node_kernel, dim3((unsigned)mk::ceil_div(nnodes, 256)), dim3(256),
+                       0, s, D1.as<float>(), I1.as<int64_t>(), nnodes, k, node0, D, I);
+    MK_LAUNCHED();
+    return MK_OK;
 }
 
 extern "C" mk_status mk_debug_pool_drops(int64_t* count) {
