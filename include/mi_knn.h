@@ -99,6 +99,25 @@ mk_status mk_knn_search(const float* xq, int64_t nq, const float* xb, int64_t nb
                         int32_t k, mk_metric metric, float* D, int64_t* I, mk_stream_t stream);
 
 /*
+ * As mk_knn_search, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Results are identical to mk_knn_search on the same arguments.  The call
+ * allocates nothing: its scratch (the database norms for L2, the chunk partial
+ * keys and the rank points, sized as documented for mk_knn_search) is carved
+ * from one fixed device array of MK_NOALLOC_SCRATCH_BYTES per GPU, which the
+ * library holds until the process ends.  A call whose scratch would exceed it
+ * returns MK_ERR_UNSUPPORTED before anything is enqueued (split the queries).
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (concurrent streams or host threads) race and must be serialised by the
+ * caller; successive calls on one stream are safe.  The first call on a
+ * device looks up the array's device address (no allocation).
+ */
+#define MK_NOALLOC_SCRATCH_BYTES (64u << 20)
+mk_status mk_knn_search_noalloc(const float* xq, int64_t nq, const float* xb, int64_t nb,
+                                int32_t d, int32_t k, mk_metric metric, float* D, int64_t* I,
+                                mk_stream_t stream);
+
+/*
  * As mk_knn_search, with the database norms ||y_i||^2 supplied by the caller
  * (e.g. from mk_norms on a resident database; ignored for MK_METRIC_IP and
  * may then be NULL).  yn [nb] float32.

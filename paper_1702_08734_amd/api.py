@@ -40,6 +40,7 @@ _SIGS = {
     "mk_norms": [_vp, _i64, _i32, _vp, _vp],
     "mk_kselect": [_vp, _i64, _i64, _i32, _i32, _vp, _vp, _vp],
     "mk_knn_search": [_vp, _i64, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
+    "mk_knn_search_noalloc": [_vp, _i64, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
     "mk_knn_graph": [_vp, _i64, _i32, _i32, _i32, _i64, _i64, _vp, _vp, _vp],
     "mk_ivfpq_knn_graph": [_vp, _vp, _i64, _i64, _i32, _i32, _vp, _vp, _vp],
     "mk_knn_search_prenorm": [_vp, _i64, _vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
@@ -188,6 +189,25 @@ def knn_graph(xb: torch.Tensor, k: int, metric: str = "l2", node0: int = 0,
     I = _out((nnodes, k), torch.int64, xb)
     _call("mk_knn_graph", _ptr(xb), nb, d, k, METRICS[metric], node0, nnodes, _ptr(D), _ptr(I),
           _stream())
+    return D, I
+
+
+def knn_search_noalloc(xq: torch.Tensor, xb: torch.Tensor, k: int, metric: str = "l2",
+                       D: torch.Tensor | None = None, I: torch.Tensor | None = None):
+    """Exact k-NN through the allocation-free entry point (the library's fixed
+    scratch array); D and I may be passed in preallocated."""
+    _dev(xq, torch.float32, "xq")
+    _dev(xb, torch.float32, "xb")
+    nq, d = xq.shape
+    nb = xb.shape[0]
+    if nb and xb.shape[1] != d:
+        raise ValueError("xq and xb dimensions differ")
+    D = _out((nq, k), torch.float32, xq) if D is None else _dev(D, torch.float32, "D")
+    I = _out((nq, k), torch.int64, xq) if I is None else _dev(I, torch.int64, "I")
+    if tuple(D.shape) != (nq, k) or tuple(I.shape) != (nq, k):
+        raise ValueError("D and I must be [nq, k]")
+    _call("mk_knn_search_noalloc", _ptr(xq), nq, _ptr(xb), nb, d, k, METRICS[metric], _ptr(D),
+          _ptr(I), _stream())
     return D, I
 
 

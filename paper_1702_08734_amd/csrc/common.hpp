@@ -50,12 +50,17 @@ const char* get_error();
     } while (0)
 
 // A caller-provided block of device memory that scratch buffers are carved
-// from in order (256-byte aligned) instead of being allocated.
+// from in order (256-byte aligned) instead of being allocated.  A sizing
+// arena (sizing = true) hands out null pointers and only adds up the bytes a
+// call would carve; code that receives one returns before launching work.
 struct Arena {
     unsigned char* base = nullptr;
     size_t size = 0;
     size_t used = 0;
+    bool sizing = false;
 };
+
+inline bool sizing_only(const Arena* a) { return a && a->sizing; }
 
 // Device scratch: stream-ordered allocations freed on the same stream when
 // they go out of scope (so a call never synchronises to release them), or,
@@ -72,6 +77,12 @@ struct Scratch {
         if (bytes == 0) bytes = 256;
         if (arena) {
             const size_t start = (arena->used + 255) & ~(size_t)255;
+            if (arena->sizing) {
+                ptr = nullptr;
+                arena->used = start + bytes;
+                owned = false;
+                return MK_OK;
+            }
             if (start > arena->size || bytes > arena->size - start) {
                 set_error("scratch of " + std::to_string(bytes) + " bytes does not fit the " +
                           std::to_string(arena->size) + "-byte workspace (" +

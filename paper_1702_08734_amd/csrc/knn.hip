@@ -96,8 +96,10 @@ mk_status knn_search(const float* xq, int64_t nq, const float* xb, const float* 
     if (l2 && !yn && nb > 0) {
         mk_status st = norms.alloc(sizeof(float) * (size_t)nb, s, arena);
         if (st != MK_OK) return st;
-        st = launch_norms(xb, nb, d, norms.as<float>(), s);
-        if (st != MK_OK) return st;
+        if (!sizing_only(arena)) {
+            st = launch_norms(xb, nb, d, norms.as<float>(), s);
+            if (st != MK_OK) return st;
+        }
         yn = norms.as<float>();
     }
     if (d <= 32) return knn_dispatch_k<32>(xq, nq, xb, yn, nb, d, k, l2, vec, D, I, s, arena);
@@ -205,6 +207,57 @@ extern "C" mk_status mk_knn_search_prenorm(const float* xq, int64_t nq, const fl
                "L2 search needs the database norms");
     return mk::knn_search(xq, nq, xb, yn, nb, d, k, metric, D, I,
                           static_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------- allocation-free search
+// The scratch of mk_knn_search_noalloc: database norms, chunk partial keys
+// and rank points of one call, carved from a fixed array that every GPU the
+// library runs on holds until the process ends.  In host code the array's
+// name is not a device address; only the address returned by
+// hipGetSymbolAddress on the device in question is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[MK_NOALLOC_SCRATCH_BYTES];
+
+namespace mk {
+namespace {
+std::vector<unsigned char*> g_scratch_dev;  // per device id; null until looked up
+}  // namespace
+
+mk_status noalloc_scratch(unsigned char** out) {
+    int dev = 0;
+    MK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_sym_mu);
+    if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        MK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        MK_REQUIRE(p, MK_ERR_DEVICE, "no device address for the search scratch array");
+        g_scratch_dev[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return MK_OK;
+}
+}  // namespace mk
+
+extern "C" mk_status mk_knn_search_noalloc(const float* xq, int64_t nq, const float* xb,
+                                           int64_t nb, int32_t d, int32_t k, mk_metric metric,
+                                           float* D, int64_t* I, mk_stream_t stream) {
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    // Size the call first (validates the arguments, launches nothing).
+    mk::Arena need;
+    need.sizing = true;
+    MK_TRY(mk::knn_search(xq, nq, xb, nullptr, nb, d, k, metric, D, I, s, &need));
+    if (nq == 0) return MK_OK;
+    MK_REQUIRE(need.used <= (size_t)MK_NOALLOC_SCRATCH_BYTES, MK_ERR_UNSUPPORTED,
+               "the search needs " + std::to_string(need.used) +
+                   " bytes of scratch, more than the " +
+                   std::to_string((size_t)MK_NOALLOC_SCRATCH_BYTES) +
+                   "-byte fixed array; split the queries into smaller batches");
+    unsigned char* base = nullptr;
+    MK_TRY(mk::noalloc_scratch(&base));
+    mk::Arena arena;
+    arena.base = base;
+    arena.size = MK_NOALLOC_SCRATCH_BYTES;
+    return mk::knn_search(xq, nq, xb, nullptr, nb, d, k, metric, D, I, s, &arena);
 }
 
 extern "C" mk_status mk_knn_graph(const float* xb, int64_t nb, int32_t d, int32_t k,

@@ -24,6 +24,7 @@ mk_status knn_launch(const float* xq, int64_t nq, const float* xb, const float* 
     mk_status st = part.alloc(sizeof(uint64_t) * (size_t)nq * (size_t)nchunks * S::ROW, stream, arena);
     if (st != MK_OK) return st;
     MK_TRY(bound.alloc(sizeof(uint32_t) * (size_t)bound_words(KR, nq, nchunks), stream, arena));
+    if (sizing_only(arena)) return MK_OK;
     MK_TRY(clear_bounds(KR, bound.as<uint32_t>(), nq, nchunks, stream));
     const int64_t nblocks = nqb * nchunks;
     MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
