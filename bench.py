@@ -33,6 +33,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+FP8_MFMA_PEAK_TFLOPS = 5000.0
 KS = (1, 32, 256, 1024)
 PMC_FILE = os.path.join(ROOT, "profiles", "knn_fused_exact_large_pmc.json")
 KERNEL_SOURCES = ["knn.hip", "fused.hpp", "wave_select.hpp", "kselect.hpp"]
@@ -59,44 +61,79 @@ def traffic_from_counters(launch_flops_per_byte=None):
     return rec.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(xq, xb, target_s: float):
-    import numpy as np
+    """The float64 oracle (direct-form distances, full sort per query) on a
+    bounded sample of the queries against the full database: all host cores
+    (OpenMP over queries) and one thread."""
     import oracle
     d = xq.shape[1]
     nb = xb.shape[0]
-    n = 16
-    t0 = time.perf_counter()
-    oracle.knn(xq[:n], xb, 32)
-    dt = time.perf_counter() - t0
-    n2 = int(max(16, min(2000, n * target_s / max(dt, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.knn(xq[n:n + n2], xb, 32)
-    dt2 = time.perf_counter() - t0
+    cores = oracle.get_threads()
+
+    def rate(q0, n):
+        t0 = time.perf_counter()
+        oracle.knn(xq[q0:q0 + n], xb, 32)
+        dt = time.perf_counter() - t0
+        return 2.0 * n * nb * d / dt / 1e12, dt
+
+    _, dt = rate(0, 16)
+    n_all = int(max(16, min(2000, 16 * 0.75 * target_s / max(dt, 1e-3))))
+    all_rate, dt_all = rate(16, n_all)
+    oracle.set_threads(1)
+    try:
+        _, dt = rate(16 + n_all, 1)
+        n_one = int(max(1, min(200, 0.25 * target_s / max(dt, 1e-3))))
+        one_rate, dt_one = rate(17 + n_all, n_one)
+    finally:
+        oracle.set_threads(cores)
     return {
-        "value": 2.0 * n2 * nb * d / dt2 / 1e12,
+        "value": all_rate,
         "unit": "TFLOP/s",
-        "cores": oracle.get_threads(),
+        "cores": cores,
         "kind": "oracle",
-        "sample": f"{n2} of {xq.shape[0]} queries against the full {nb}-row database, k=32 "
-                  f"(float64 direct-form distances + full sort per query; {dt2:.1f} s)",
+        "cpu_model": cpu_model(),
+        "single_thread_value": one_rate,
+        "sample": f"{n_all} of {xq.shape[0]} queries against the full {nb}-row database, k=32, "
+                  f"on {cores} threads ({dt_all:.1f} s); single thread: {n_one} queries "
+                  f"({dt_one:.1f} s). float64 direct-form distances + full sort per query",
     }
 
 
 HBM_PEAK_GBS = 8000.0
 
 
+T_START = time.perf_counter()
+
+
 def progress(msg: str) -> None:
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    print(f"[bench {time.perf_counter() - T_START:7.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
-def _timed(torch, fn, reps):
-    fn()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
+def _timed(torch, fn, reps=5, warmup=1):
+    """Warm-up, then `reps` timed calls each bracketed by device syncs:
+    (median seconds, min seconds)."""
+    import statistics
+    for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / reps
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return statistics.median(ts), min(ts)
 
 
 def kselect_section(api, synth, torch):
@@ -110,9 +147,10 @@ def kselect_section(api, synth, torch):
         for k in (100, 1000):
             if k > length:
                 continue
-            dt = _timed(torch, lambda: api.kselect(a, k), 3)
+            dt, dmin = _timed(torch, lambda: api.kselect(a, k))
             gbs = (a.numel() * 4 + a.shape[0] * k * 12) / dt / 1e9
-            row[f"k{k}"] = {"ms": round(dt * 1e3, 3), "GB/s": round(gbs, 1),
+            row[f"k{k}"] = {"ms": round(dt * 1e3, 3), "ms_min": round(dmin * 1e3, 3),
+                            "GB/s": round(gbs, 1),
                             "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
         res["lengths"][str(length)] = row
         del a
@@ -125,49 +163,77 @@ def small_exact_section(api, synth, torch):
     w = synth.exact_small()
     xb = torch.from_numpy(w["xb"]).cuda()
     xq = torch.from_numpy(w["xq"]).cuda()
-    dt = _timed(torch, lambda: api.knn_search(xq, xb, w["k"]), 20)
+    dt, dmin = _timed(torch, lambda: api.knn_search(xq, xb, w["k"]), 20, 3)
     return {"workload": "50,000 x 64 N(0,1), 500 queries, k = 10, L2",
-            "latency_ms": round(dt * 1e3, 3),
+            "latency_ms": round(dt * 1e3, 3), "latency_ms_min": round(dmin * 1e3, 3),
             "TFLOP/s": round(2 * 500 * 50_000 * 64 / dt / 1e12, 2)}
 
 
-def lowp_section(api, synth, torch):
+def lowp_section(api, synth, torch, oracle_queries=32):
     """BF16 / FP8-E4M3 brute force on the matrix cores with an exact FP32
     re-rank of the R = 4k best against FP32 brute force: 20,000,000 x 96
-    unit-norm rows of a 2,000-component mixture, 10,000 queries, k = 100."""
+    unit-norm rows of a 2,000-component mixture, 10,000 queries, k = 100.
+    Every variant: one warm-up, 5 timed runs (median, min).  Recall@100 and
+    the relative distance error of the returned distances are taken against
+    the float64 oracle on a sample of queries."""
     import numpy as np
+    import oracle
     w = synth.lowp_workload()
     progress("lowp: generating 20,000,000 x 96 unit-norm mixture")
-    xb = torch.from_numpy(w["xb"]).cuda()
-    xq = torch.from_numpy(w["xq"]).cuda()
+    xb_h, xq_h = w["xb"], w["xq"]
+    xb = torch.from_numpy(xb_h).cuda()
+    xq = torch.from_numpy(xq_h).cuda()
     k, R = w["k"], w["R"]
     nq, nb, d = xq.shape[0], xb.shape[0], xb.shape[1]
     flop = 2.0 * nq * nb * d
+    sample = np.linspace(0, nq - 1, oracle_queries).astype(np.int64)
     res = {"workload": "20,000,000 x 96 unit-norm 2,000-component mixture, 10,000 queries, "
-                       f"k = {k}, re-rank R = {R}", "metrics": {}}
+                       f"k = {k}, re-rank R = {R}",
+           "oracle_sample": f"{oracle_queries} queries (evenly spaced) against the full database, "
+                            "float64 direct form, full sort", "metrics": {}}
+
+    def vs_oracle(D, I, Do, Io):
+        D = D.cpu().numpy()[sample].astype(np.float64)
+        I = I.cpu().numpy()[sample]
+        rec = float(np.mean([len(set(I[j]) & set(Io[j])) / k for j in range(len(sample))]))
+        # float64 value of the returned rows, the same index's oracle distance
+        x = xq_h[sample].astype(np.float64)
+        y = xb_h[I].astype(np.float64)
+        if metric == "l2":
+            ref = ((y - x[:, None, :]) ** 2).sum(-1)
+        else:
+            ref = (y * x[:, None, :]).sum(-1)
+        err = np.abs(D - ref) / np.maximum(np.abs(ref), 1e-30)
+        return rec, float(err.max()), float(err.mean())
+
     for metric in w["metrics"]:
+        progress(f"lowp: oracle on {oracle_queries} queries ({metric})")
+        Do, Io = oracle.knn(xq_h[sample], xb_h, k,
+                            oracle.METRIC_L2 if metric == "l2" else oracle.METRIC_IP)
         progress(f"lowp: fp32 {metric}")
-        t0 = time.perf_counter()
-        De, Ie = api.knn_search(xq, xb, k, metric)
-        torch.cuda.synchronize()
-        t_fp32 = time.perf_counter() - t0
-        Ie = Ie.cpu().numpy()
-        row = {"fp32": {"ms": round(t_fp32 * 1e3, 1), "TFLOP/s": round(flop / t_fp32 / 1e12, 2)}}
+        t32, t32min = _timed(torch, lambda: api.knn_search(xq, xb, k, metric))
+        D, I = api.knn_search(xq, xb, k, metric)
+        rec, emax, emean = vs_oracle(D, I, Do, Io)
+        row = {"fp32": {"ms": round(t32 * 1e3, 1), "ms_min": round(t32min * 1e3, 1),
+                        "TFLOP/s": round(flop / t32 / 1e12, 2),
+                        "recall_at_100_vs_oracle": round(rec, 4),
+                        "max_rel_dist_err": emax, "mean_rel_dist_err": emean}}
         for prec in ("bf16", "fp8"):
             progress(f"lowp: {prec} {metric}")
             lp, inv = api.quantize_rows(xb, prec)
-            api.knn_search_lowp(xq, xb, lp, inv, k, R, prec, metric)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
+            dt, dmin = _timed(torch, lambda: api.knn_search_lowp(xq, xb, lp, inv, k, R, prec,
+                                                                 metric))
             D, I = api.knn_search_lowp(xq, xb, lp, inv, k, R, prec, metric)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            I = I.cpu().numpy()
-            rec = float(np.mean([len(set(I[j]) & set(Ie[j])) / k for j in range(nq)]))
+            rec, emax, emean = vs_oracle(D, I, Do, Io)
             # distances are the exact FP32 direct form of the returned rows
-            row[prec] = {"ms": round(dt * 1e3, 1), "TFLOP/s": round(flop / dt / 1e12, 2),
-                         "speedup_vs_fp32": round(t_fp32 / dt, 2),
-                         "recall_at_100_vs_fp32_exact": round(rec, 4)}
+            row[prec] = {"ms": round(dt * 1e3, 1), "ms_min": round(dmin * 1e3, 1),
+                         "TFLOP/s": round(flop / dt / 1e12, 2),
+                         "frac_mfma_peak": round(flop / dt / 1e12 /
+                                                 (BF16_MFMA_PEAK_TFLOPS if prec == "bf16"
+                                                  else FP8_MFMA_PEAK_TFLOPS), 4),
+                         "speedup_vs_fp32": round(t32 / dt, 2),
+                         "recall_at_100_vs_oracle": round(rec, 4),
+                         "max_rel_dist_err": emax, "mean_rel_dist_err": emean}
             del lp, inv
             torch.cuda.empty_cache()
         res["metrics"][metric] = row
@@ -213,7 +279,7 @@ def ivfpq_section(api, synth, torch):
     for nprobe in w["nprobes"]:
         progress(f"ivfpq: nprobe {nprobe}")
         api.profile_enable(True)
-        dt = _timed(torch, lambda: ix.search(xq, k, nprobe), 3)
+        dt, dmin = _timed(torch, lambda: ix.search(xq, k, nprobe))
         api.profile_enable(False)
         scan_ms, scan_n = api.profile_read("ivf_scan")
         r1, r2 = recalls(ix.search(xq, k, nprobe)[1])
@@ -221,25 +287,28 @@ def ivfpq_section(api, synth, torch):
         scanned = int(sizes[probe[:, :nprobe]].sum())
         code_bytes = scanned * w["M"]
         scan_s = scan_ms / max(scan_n, 1) / 1e3
-        curve.append({"nprobe": nprobe, "ms": round(dt * 1e3, 3), "qps": round(nq / dt, 1),
+        curve.append({"nprobe": nprobe, "ms": round(dt * 1e3, 3), "ms_min": round(dmin * 1e3, 3),
+                      "qps": round(nq / dt, 1),
                       "recall_at_10": r1, "ten_intersection": r2,
                       "scanned_codes": scanned,
                       "scan_GB/s": round(code_bytes / scan_s / 1e9, 1) if scan_s > 0 else None,
                       "scan_frac_hbm": round(code_bytes / scan_s / 1e9 / HBM_PEAK_GBS, 4)
                       if scan_s > 0 else None})
         for R in w["rerank"]:
-            dt = _timed(torch, lambda: ix.search_rerank(xq, 10, nprobe, R, xb), 3)
+            dt, dmin = _timed(torch, lambda: ix.search_rerank(xq, 10, nprobe, R, xb))
             r1, r2 = recalls(ix.search_rerank(xq, 10, nprobe, R, xb)[1])
             rerank.append({"nprobe": nprobe, "R": R, "ms": round(dt * 1e3, 3),
+                           "ms_min": round(dmin * 1e3, 3),
                            "qps": round(nq / dt, 1), "recall_at_10": r1,
                            "ten_intersection": r2})
+    graph = graph_section(api, torch, ix, xb, w, t_train + t_add)
     learned = learned_probe_section(api, synth, torch, ix, xb, xq, w, recalls)
     serving = serving_section(api, synth, torch, ix, xb, xq, w, learned)
     del xb
     torch.cuda.empty_cache()
     best = [c for c in curve if c["recall_at_10"] >= 0.9]
     best_rr = sorted((c for c in rerank if c["recall_at_10"] >= 0.9), key=lambda c: -c["qps"])
-    return {"learned_probe": learned, "serving": serving,
+    return {"learned_probe": learned, "serving": serving, "knn_graph": graph,
             "workload": "10,000,000 x 128 mixture, nlist 4096, PQ 16 x 8 bit, 10,000 queries, "
                         "k = 100 (ADC) / k = 10 after exact re-rank of R, "
                         "train 500,000 rows x 20 iterations",
@@ -253,6 +322,34 @@ def ivfpq_section(api, synth, torch):
                                                  "R": best_rr[0]["R"]} if best_rr else None)}
 
 
+def graph_section(api, torch, ix, xb, w, build_s):
+    """k-NN graph (k = 10, a node is not its own neighbour) of every database
+    vector searched against the IVFADC index, as in Section 6.5: build time
+    (train + add) plus search time, and the 10-intersection with the exact
+    graph on 10,000 nodes (the first 10,000 rows; the rows are i.i.d. draws).
+    Settings (nprobe, R): R = 0 is the paper's ADC-only graph, R > 0 re-ranks
+    an R-entry ADC short list exactly."""
+    import numpy as np
+    n, k, ns = xb.shape[0], 10, 10_000
+    progress("knn graph: exact rows of 10,000 sample nodes")
+    ge = api.knn_graph(xb, k, "l2", 0, ns)[1].cpu().numpy()
+    rows = []
+    for nprobe, R in w["graph_settings"]:
+        progress(f"knn graph: all {n} nodes, nprobe {nprobe}, R {R}")
+        ix.knn_graph(xb, k, nprobe, 0, 1_000_000, R=R)  # warm-up on a tenth
+        dt, dmin = _timed(torch, lambda: ix.knn_graph(xb, k, nprobe, R=R), 3, warmup=0)
+        I = ix.knn_graph(xb, k, nprobe, 0, ns, R=R)[1].cpu().numpy()
+        inter = float(np.mean([len(set(I[j]) & set(ge[j])) / k for j in range(ns)]))
+        rows.append({"nprobe": nprobe, "R": R, "search_s": round(dt, 3),
+                     "search_s_min": round(dmin, 3), "nodes_per_s": round(n / dt, 1),
+                     "end_to_end_s": round(build_s + dt, 3),
+                     "ten_intersection": round(inter, 4)})
+    return {"nodes": n, "k": k, "build_s": round(build_s, 3), "curve": rows,
+            "quality": "10-intersection with the exact graph on 10,000 nodes",
+            "timing": "one warm-up on 1,000,000 nodes, then 3 timed builds of the whole graph "
+                      "(median, min)"}
+
+
 def learned_probe_section(api, synth, torch, ix, xb, xq, w, recalls):
     """Learned per-query probe count vs the best fixed probe count, both with
     the same exact re-rank depth, at recall@10 >= 0.9 (true nearest
@@ -262,9 +359,10 @@ def learned_probe_section(api, synth, torch, ix, xb, xq, w, recalls):
     # fixed probe counts with the same re-rank depth
     fixed = []
     for nprobe in w["learn_fixed_nprobes"]:
-        dt = _timed(torch, lambda: ix.search_rerank(xq, k, nprobe, R, xb), 3)
+        dt, dmin = _timed(torch, lambda: ix.search_rerank(xq, k, nprobe, R, xb))
         r1, r2 = recalls(ix.search_rerank(xq, k, nprobe, R, xb)[1])
-        fixed.append({"nprobe": nprobe, "ms": round(dt * 1e3, 3), "qps": round(nq / dt, 1),
+        fixed.append({"nprobe": nprobe, "ms": round(dt * 1e3, 3), "ms_min": round(dmin * 1e3, 3),
+                      "qps": round(nq / dt, 1),
                       "recall_at_10": r1, "ten_intersection": r2})
     progress("learned probe: labels for training queries")
     base = w["base"]
@@ -301,10 +399,11 @@ def learned_probe_section(api, synth, torch, ix, xb, xq, w, recalls):
     best_fixed = [c for c in fixed if c["recall_at_10"] >= 0.9]
     out["qps_fixed_at_0.9"] = max((c["qps"] for c in best_fixed), default=None)
     if delta is not None:
-        dt = _timed(torch, lambda: ix.search_learned(net, delta, xq, k, cap, R, xb), 3)
+        dt, dmin = _timed(torch, lambda: ix.search_learned(net, delta, xq, k, cap, R, xb))
         _, I, tau = ix.search_learned(net, delta, xq, k, cap, R, xb)
         r1, r2 = recalls(I)
-        out.update({"ms": round(dt * 1e3, 3), "qps_learned": round(nq / dt, 1),
+        out.update({"ms": round(dt * 1e3, 3), "ms_min": round(dmin * 1e3, 3),
+                    "qps_learned": round(nq / dt, 1),
                     "recall_at_10": r1, "ten_intersection": r2,
                     "mean_nprobe": round(float(tau.float().mean().item()), 2)})
     # device time per kernel of one search at the fixed count reaching 0.9 and
@@ -404,11 +503,9 @@ def serving_section(api, synth, torch, ix, xb, xq, w, learned):
     return res
 
 
-def ivf_large_run(api, synth, torch):
-    """IVFADC at 50,000,000 x 128 (16,384 lists, PQ 16): fixed vs learned probe
-    count at R@10 >= 0.9 with the same exact re-rank depth, and serving
-    latencies; one JSON record."""
-    import numpy as np
+def build_large_index(api, synth, torch):
+    """The 50,000,000 x 128 IVFADC index (16,384 lists, PQ 16 x 8 bit) with its
+    database and queries resident on the device."""
     progress("ivf-large: generating 50,000,000 x 128 mixture")
     w = synth.ivfpq_large_workload()
     xb = torch.from_numpy(w["xb"]).cuda()
@@ -427,9 +524,23 @@ def ivf_large_run(api, synth, torch):
     ix.add(xb)
     torch.cuda.synchronize()
     t_add = time.perf_counter() - t0
+    return w, ix, xb, xq, t_train, t_add
+
+
+def ivf_large_run(api, synth, torch):
+    """IVFADC at 50,000,000 x 128 (16,384 lists, PQ 16): the ADC scan curve
+    (codes 800 MB, more than the 256 MB last-level cache, so list scans read
+    HBM), fixed vs learned probe count at R@10 >= 0.9 with the same exact
+    re-rank depth, and serving latencies."""
+    import numpy as np
+    w, ix, xb, xq, t_train, t_add = build_large_index(api, synth, torch)
     progress("ivf-large: ground truth")
     gt = api.knn_search(xq, xb, 10)[1].cpu().numpy()
     nq = xq.shape[0]
+    offs, _, _ = ix.get_lists()
+    sizes = np.diff(offs)
+    _, probe = api.knn_search(xq, torch.from_numpy(ix.get_quantizers()[0]).cuda(), 64)
+    probe = probe.cpu().numpy()
 
     def recalls(I):
         I = I.cpu().numpy()[:, :10]
@@ -437,13 +548,46 @@ def ivf_large_run(api, synth, torch):
         r2 = float(np.mean([len(set(gt[j]) & set(I[j])) / 10 for j in range(nq)]))
         return round(r1, 4), round(r2, 4)
 
+    curve = []
+    for nprobe in (8, 32, 64):
+        progress(f"ivf-large: ADC scan nprobe {nprobe}")
+        api.profile_enable(True)
+        dt, dmin = _timed(torch, lambda: ix.search(xq, 100, nprobe))
+        api.profile_enable(False)
+        scan_ms, scan_n = api.profile_read("ivf_scan")
+        scanned = int(sizes[probe[:, :nprobe]].sum())
+        alg = scanned * (w["M"] + 4)  # code bytes + stored term 1 per entry
+        scan_s = scan_ms / max(scan_n, 1) / 1e3
+        r1, r2 = recalls(ix.search(xq, 100, nprobe)[1])
+        curve.append({"nprobe": nprobe, "k": 100, "ms": round(dt * 1e3, 3),
+                      "ms_min": round(dmin * 1e3, 3), "qps": round(nq / dt, 1),
+                      "recall_at_10": r1, "ten_intersection": r2, "scanned_entries": scanned,
+                      "scan_ms": round(scan_s * 1e3, 3),
+                      "scan_GB/s": round(alg / scan_s / 1e9, 1) if scan_s > 0 else None,
+                      "scan_frac_hbm": round(alg / scan_s / 1e9 / HBM_PEAK_GBS, 4)
+                      if scan_s > 0 else None})
     learned = learned_probe_section(api, synth, torch, ix, xb, xq, w, recalls)
     serving = serving_section(api, synth, torch, ix, xb, xq, w, learned)
+    del xb
+    torch.cuda.empty_cache()
     return {"metric": "IVFADC queries/s at R@10 >= 0.9 (learned vs fixed probe count, exact re-rank)",
             "workload": "50,000,000 x 128 1,000-component mixture, nlist 16384, PQ 16 x 8 bit, "
-                        "10,000 queries, k = 10, re-rank R = 256",
+                        f"10,000 queries, k = 10, re-rank R = {w['learn_rerank']}",
             "train_s": round(t_train, 2), "add_s": round(t_add, 2),
-            "learned_probe": learned, "serving": serving}
+            "list_size_mean": float(sizes.mean()), "list_size_max": int(sizes.max()),
+            "adc_curve": curve, "learned_probe": learned, "serving": serving}
+
+
+def ivf_large_scan_profile(api, synth, torch):
+    """Only the ADC list scans of the 50,000,000-vector index at nprobe 16
+    and 64 (for hardware-counter runs restricted to the scan kernel)."""
+    _, ix, xb, xq, _, _ = build_large_index(api, synth, torch)
+    for nprobe in (16, 64):
+        progress(f"ivf-large scan profile: nprobe {nprobe}")
+        for _ in range(3):
+            ix.search(xq, 100, nprobe)
+        torch.cuda.synchronize()
+    return {"profiled": "ivf_scan at nprobe 16 and 64, 3 searches each, 10,000 queries, k = 100"}
 
 
 def main() -> int:
@@ -459,6 +603,10 @@ def main() -> int:
                     help="only copy 1 GiB device to device (HBM byte-counter calibration)")
     ap.add_argument("--ivf-large", action="store_true",
                     help="only the 50,000,000-vector IVFADC learned-probe and serving run")
+    ap.add_argument("--ivf-large-scan", action="store_true",
+                    help="only the list scans of the 50,000,000-vector index (profiling)")
+    ap.add_argument("--skip-large", action="store_true",
+                    help="leave out the 50,000,000-vector IVFADC section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are "
@@ -478,6 +626,9 @@ def main() -> int:
 
     if args.ivf_large:
         print(json.dumps(ivf_large_run(api, synth, torch)), flush=True)
+        return 0
+    if args.ivf_large_scan:
+        print(json.dumps(ivf_large_scan_profile(api, synth, torch)), flush=True)
         return 0
 
     progress("exact: generating 1,000,000 x 128 mixture")
@@ -564,8 +715,11 @@ def main() -> int:
     del xq, xb
     torch.cuda.empty_cache()
     if not args.skip_extra:
-        for name, fn in (("small_exact", small_exact_section), ("kselect", kselect_section),
-                         ("ivfpq", ivfpq_section), ("lowp", lowp_section)):
+        sections = [("small_exact", small_exact_section), ("kselect", kselect_section),
+                    ("ivfpq", ivfpq_section), ("lowp", lowp_section)]
+        if not args.skip_large:
+            sections.append(("ivf_large", ivf_large_run))
+        for name, fn in sections:
             try:
                 out["extra"][name] = fn(api, synth, torch)
             except Exception as e:  # the headline value stands on its own

@@ -99,6 +99,28 @@ mk_status mk_knn_search(const float* xq, int64_t nq, const float* xb, int64_t nb
                         int32_t k, mk_metric metric, float* D, int64_t* I, mk_stream_t stream);
 
 /*
+ * Exact k-NN against a database held in host memory (Section 5.1: inputs
+ * larger than the GPU's memory stream in from the CPU).  The database is
+ * copied in chunks of chunk_rows rows into two device buffers on a second
+ * stream, the copy of chunk c + 1 overlapping the fused search of chunk c
+ * on `stream`; each chunk's k best (mk_knn_search semantics, rows numbered
+ * globally) are kept and one final k-selection over the chunks' lists keyed
+ * (distance, row) gives the result.  Same contract as mk_knn_search (squared
+ * L2 ascending or inner product descending, ties to the lower row, padding).
+ *   xq [nq, d] float32 DEVICE, xb_host [nb, d] float32 HOST memory (pinned,
+ *   e.g. hipHostMalloc, for the copies to overlap the searches),
+ *   D [nq, k] float32 and I [nq, k] int64 DEVICE.
+ * nb < 2^32 - 1; 1 <= chunk_rows < 2^31.  Device scratch: two chunk buffers
+ * (2 chunk_rows d 4 bytes), nq k 12 bytes per chunk plus 8 bytes per key of
+ * nq k ceil(nb / chunk_rows), and mk_knn_search's scratch for one chunk.
+ * Synchronises `stream` before returning (the internal copy stream and its
+ * events are released).
+ */
+mk_status mk_knn_search_host(const float* xq, int64_t nq, const float* xb_host, int64_t nb,
+                             int32_t d, int32_t k, mk_metric metric, int64_t chunk_rows,
+                             float* D, int64_t* I, mk_stream_t stream);
+
+/*
  * As mk_knn_search, for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
  * Results are identical to mk_knn_search on the same arguments.  The call
@@ -180,7 +202,7 @@ mk_status mk_pq_encode(const float* r, int64_t n, int32_t d, int32_t M, const fl
  * Low-precision brute force with exact re-rank (an extension of the exact
  * search of Section 5.1; the paper computes distances in FP32 only).
  * ------------------------------------------------------------------------ */
-typedef enum { MK_PREC_FP32 = 0, MK_PREC_BF16 = 1, MK_PREC_FP8E4M3 = 2 } mk_precision;
+typedef enum { MK_PREC_FP32 = 0, MK_PREC_BF16 = 1, MK_PREC_FP8E4M3 = 2, MK_PREC_FP16 = 3 } mk_precision;
 
 /* Row stride, in elements, of low-precision copies: d rounded up to 16. */
 int32_t mk_lowp_stride(int32_t d);
@@ -223,8 +245,9 @@ mk_status mk_knn_search_lowp(const float* xq, int64_t nq, const float* xb, const
  * ------------------------------------------------------------------------ */
 typedef struct mk_ivfpq mk_ivfpq;
 
-/* d >= 1, nlist >= 1, M in {4, 8, ..., 64} with d % M == 0 (Section 5.2
- * allows any multiple of 4 up to 64 sub-quantizers).  Allocates nothing on
+/* d >= 1, nlist >= 1, M in {4, 8, ..., 128} with d % M == 0 (Section 5.2
+ * allows any multiple of 4 up to 64 sub-quantizers; M > 64 needs the
+ * 16-bit lookup tables of mk_ivfpq_set_scan_options to search).  Allocates nothing on
  * the device until training. */
 mk_status mk_ivfpq_create(int32_t d, int32_t nlist, int32_t M, mk_ivfpq** out);
 
@@ -259,7 +282,8 @@ int64_t mk_ivfpq_ntotal(const mk_ivfpq* index);
  * nearest of the scanned entries (Eq. 6).  D are ADC squared distances
  * (FP32), I the ids.  1 <= nprobe <= min(nlist, 1024).  The tables and the
  * per-list merge buffers must fit 64 KiB of LDS: 1024 M + 32 k <= 65536
- * bytes (any k for M <= 32, k <= 256 for M = 64).
+ * bytes (any k for M <= 32, k <= 256 for M = 64); with 16-bit tables
+ * (mk_ivfpq_set_scan_options) 512 M + 32 k <= 65536.
  *   xq [nq, d] float32, D [nq, k] float32, I [nq, k] int64
  */
 mk_status mk_ivfpq_search(mk_ivfpq* index, const float* xq, int64_t nq, int32_t k,
@@ -270,13 +294,16 @@ mk_status mk_ivfpq_search(mk_ivfpq* index, const float* xq, int64_t nq, int32_t 
  * indexed vectors (Section 6.5): each added vector with id i (row i of xb,
  * the array that was added, ids 0 .. ntotal - 1) is searched against the
  * index as by mk_ivfpq_search, and entries with id i are skipped, so a node
- * is never its own neighbour.  Nodes are processed in batches of 32768
- * queries on `stream`.
- *   xb [ntotal, d] float32, D [nnodes, k] float32 (ADC distances),
- *   I [nnodes, k] int64.  node0 + nnodes <= ntotal.
+ * is never its own neighbour.  With R > 0 each node's short list of the R
+ * best entries by ADC distance (itself excluded) is re-ranked exactly
+ * against xb as by mk_ivfpq_search_rerank.  Nodes are processed in batches
+ * of 32768 queries on `stream`.
+ *   xb [ntotal, d] float32, D [nnodes, k] float32 (ADC distances, or exact
+ *   squared distances when R > 0), I [nnodes, k] int64.
+ * node0 + nnodes <= ntotal; R = 0 or k <= R <= 1024.
  */
 mk_status mk_ivfpq_knn_graph(mk_ivfpq* index, const float* xb, int64_t node0, int64_t nnodes,
-                             int32_t k, int32_t nprobe, float* D, int64_t* I,
+                             int32_t k, int32_t nprobe, int32_t R, float* D, int64_t* I,
                              mk_stream_t stream);
 
 /*
@@ -319,6 +346,29 @@ mk_status mk_ivfpq_set_quantizers(mk_ivfpq* index, const float* coarse, const fl
  */
 mk_status mk_ivfpq_get_lists(const mk_ivfpq* index, int64_t* offsets, uint8_t* codes,
                              int64_t* ids);
+
+/*
+ * Write a trained index to the file `path` (Section 5.3's resident layout:
+ * the quantizers and the inverted lists).  Format, little-endian: 8-byte
+ * magic "MKIVFPQ\0", u32 version 1, i32 d, i32 nlist, i32 M, i64 ntotal,
+ * coarse centroids f32 [nlist, d], codebooks f32 [M, 256, d / M], list
+ * offsets i64 [nlist + 1], codes u8 [ntotal, M], ids i64 [ntotal].
+ * Tables derived from these (centroid norms, the term-1 tables of Eq. 11)
+ * are not stored.  Synchronises the device.  MK_ERR_STATE before training;
+ * MK_ERR_INVALID_ARG when the file cannot be written.
+ */
+mk_status mk_ivfpq_save(const mk_ivfpq* index, const char* path);
+
+/*
+ * Create an index from a file written by mk_ivfpq_save; the caller owns
+ * *out (mk_ivfpq_destroy).  The derived tables are rebuilt on the device
+ * with the kernels of train and add, so searches of the loaded index equal
+ * those of the saved one bit for bit.  Synchronises.  A file that is not an
+ * index file, is truncated, has trailing bytes or inconsistent list offsets
+ * gives MK_ERR_INVALID_ARG (checked on the host; the header before any
+ * device work) and *out = NULL.  Ids are taken as stored.
+ */
+mk_status mk_ivfpq_load(const char* path, mk_ivfpq** out);
 
 
 /* ------------------------------------------------------------------------
@@ -389,6 +439,19 @@ mk_status mk_mlp_train_epoch(mk_mlp* net, const float* F, int64_t n, const float
                              const int64_t* perm, int32_t batch, float lr, float* losses,
                              mk_stream_t stream);
 
+/*
+ * Write / read a network: 8-byte magic "MKMLP\0\0\0", u32 version 1, i32 din,
+ * i32 hidden, i32 precision, i64 Adam step count, then f32 arrays: the
+ * parameters, both Adam moments (mk_mlp_num_params each), the feature means
+ * and 1 / standard deviations [din].  A loaded network predicts and trains
+ * on exactly as the saved one.  The caller owns *out (mk_mlp_destroy).  Both
+ * synchronise the device; bad or truncated files give MK_ERR_INVALID_ARG.
+ */
+mk_status mk_mlp_save(const mk_mlp* net, const char* path);
+/* din, hidden and precision of a network; any output pointer may be NULL. */
+mk_status mk_mlp_shape(const mk_mlp* net, int32_t* din, int32_t* hidden, int32_t* prec);
+mk_status mk_mlp_load(const char* path, mk_mlp** out);
+
 /* Raw network features of nq queries: F [nq, d + 32] = [xq ; the 32
  * smallest squared coarse distances, ascending].  Needs nlist >= 32. */
 mk_status mk_ivfpq_probe_features(const mk_ivfpq* index, const float* xq, int64_t nq, float* F,
@@ -418,6 +481,33 @@ mk_status mk_ivfpq_search_learned(mk_ivfpq* index, const mk_mlp* net, float delt
 
 /* Dimension d of an index. */
 int32_t mk_ivfpq_dim(const mk_ivfpq* index);
+
+/*
+ * List-scan options of an index, used by every later search call on it
+ * (fixed or learned probe count, re-rank, k-NN graph, serving):
+ *   lut_precision  MK_PREC_FP32 (default) or MK_PREC_FP16: the per-query
+ *                  table -2 term3 of Eq. 11 staged in LDS in 16-bit floats
+ *                  (Section 5.3 notes 16-bit tables as the way to larger M):
+ *                  half the LDS and half the bytes per lookup, each entry
+ *                  rounded once (relative error 2^-11), sums in FP32.  The
+ *                  ADC distance then errs by up to 2^-11 sum_m |2 term3_m| --
+ *                  outside the 1e-5 FP32 tolerance.  Needed for M > 64
+ *                  (FP32 tables of M <= 64 fill at most 64 KiB of LDS).
+ *                  Entries must satisfy |2 term3| < 65504.
+ *   lists_per_group  probed lists of one query scanned by one workgroup:
+ *                  0 (default) chosen from the launch size (enough
+ *                  workgroups to fill the chip, at most 16 lists each), -1
+ *                  all of a query's lists (the per-query fused scan of
+ *                  Section 5.3), or a count 1..1024.
+ * Results do not depend on lists_per_group (candidates are keyed by
+ * (distance, id)).  MK_ERR_UNSUPPORTED for another precision.
+ */
+mk_status mk_ivfpq_set_scan_options(mk_ivfpq* index, mk_precision lut_precision,
+                                    int32_t lists_per_group);
+
+/* d, nlist and M of an index (e.g. one created by mk_ivfpq_load); any
+ * output pointer may be NULL. */
+mk_status mk_ivfpq_shape(const mk_ivfpq* index, int32_t* d, int32_t* nlist, int32_t* M);
 
 /*
  * Upper bound on the device workspace (bytes) that one search of nq queries

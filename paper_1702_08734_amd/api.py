@@ -41,8 +41,9 @@ _SIGS = {
     "mk_kselect": [_vp, _i64, _i64, _i32, _i32, _vp, _vp, _vp],
     "mk_knn_search": [_vp, _i64, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
     "mk_knn_search_noalloc": [_vp, _i64, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
+    "mk_knn_search_host": [_vp, _i64, _vp, _i64, _i32, _i32, _i32, _i64, _vp, _vp, _vp],
     "mk_knn_graph": [_vp, _i64, _i32, _i32, _i32, _i64, _i64, _vp, _vp, _vp],
-    "mk_ivfpq_knn_graph": [_vp, _vp, _i64, _i64, _i32, _i32, _vp, _vp, _vp],
+    "mk_ivfpq_knn_graph": [_vp, _vp, _i64, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
     "mk_knn_search_prenorm": [_vp, _i64, _vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
     "mk_kmeans_assign": [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp],
     "mk_kmeans_update": [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp],
@@ -57,6 +58,13 @@ _SIGS = {
     "mk_ivfpq_get_quantizers": [_vp, _vp, _vp],
     "mk_ivfpq_set_quantizers": [_vp, _vp, _vp, _vp],
     "mk_ivfpq_get_lists": [_vp, _vp, _vp, _vp],
+    "mk_ivfpq_set_scan_options": [_vp, _i32, _i32],
+    "mk_ivfpq_shape": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+    "mk_ivfpq_save": [_vp, ctypes.c_char_p],
+    "mk_ivfpq_load": [ctypes.c_char_p, ctypes.POINTER(_vp)],
+    "mk_mlp_save": [_vp, ctypes.c_char_p],
+    "mk_mlp_shape": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+    "mk_mlp_load": [ctypes.c_char_p, ctypes.POINTER(_vp)],
     "mk_lowp_stride": [_i32],
     "mk_quantize_rows": [_vp, _i64, _i32, _i32, _vp, _vp, _vp],
     "mk_knn_search_lowp": [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _i32,
@@ -178,6 +186,26 @@ def knn_search(xq: torch.Tensor, xb: torch.Tensor, k: int, metric: str = "l2",
     return D, I
 
 
+def knn_search_host(xq: torch.Tensor, xb_host: torch.Tensor, k: int, metric: str = "l2",
+                    chunk_rows: int = 1 << 20):
+    """Exact k-NN against a host-resident (ideally pinned) database streamed
+    to the device in chunks of chunk_rows rows; synchronises the stream."""
+    _dev(xq, torch.float32, "xq")
+    if not isinstance(xb_host, torch.Tensor) or xb_host.is_cuda:
+        raise ValueError("xb_host must be a CPU tensor")
+    if xb_host.dtype != torch.float32 or not xb_host.is_contiguous():
+        raise ValueError("xb_host must be contiguous float32")
+    nq, d = xq.shape
+    nb = xb_host.shape[0]
+    if nb and xb_host.shape[1] != d:
+        raise ValueError("xq and xb_host dimensions differ")
+    D = _out((nq, k), torch.float32, xq)
+    I = _out((nq, k), torch.int64, xq)
+    _call("mk_knn_search_host", _ptr(xq), nq, _ptr(xb_host), nb, d, k, METRICS[metric],
+          chunk_rows, _ptr(D), _ptr(I), _stream())
+    return D, I
+
+
 def knn_graph(xb: torch.Tensor, k: int, metric: str = "l2", node0: int = 0,
               nnodes: int | None = None):
     """Rows node0 .. node0 + nnodes - 1 of the exact k-NN graph of xb (a node
@@ -279,11 +307,33 @@ def pq_encode(r: torch.Tensor, codebooks: torch.Tensor) -> torch.Tensor:
 class IVFPQ:
     """Resident IVFADC index (coarse k-means + 8-bit PQ on residuals, L2)."""
 
-    def __init__(self, d: int, nlist: int, M: int):
+    def __init__(self, d: int, nlist: int, M: int, _handle=None):
         self.d, self.nlist, self.M = d, nlist, M
+        if _handle is not None:
+            self._h = _handle
+            return
         h = _vp()
         _call("mk_ivfpq_create", d, nlist, M, ctypes.byref(h))
         self._h = h
+
+    def set_scan_options(self, lut: str = "fp32", lists_per_group: int = 0) -> None:
+        """List-scan options: lookup tables in "fp32" or "fp16"; probed lists
+        per workgroup (0 automatic, -1 all of a query's lists, or a count)."""
+        _call("mk_ivfpq_set_scan_options", self._h, {"fp32": 0, "fp16": 3}[lut],
+              int(lists_per_group))
+
+    def save(self, path: str) -> None:
+        """Write the trained index (quantizers and lists) to `path`."""
+        _call("mk_ivfpq_save", self._h, os.fsencode(path))
+
+    @classmethod
+    def load(cls, path: str) -> "IVFPQ":
+        """An index read from a file written by save()."""
+        h = _vp()
+        _call("mk_ivfpq_load", os.fsencode(path), ctypes.byref(h))
+        d, nlist, M = _i32(), _i32(), _i32()
+        _call("mk_ivfpq_shape", h, ctypes.byref(d), ctypes.byref(nlist), ctypes.byref(M))
+        return cls(d.value, nlist.value, M.value, _handle=h)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -318,16 +368,17 @@ class IVFPQ:
         return D, I
 
     def knn_graph(self, xb: torch.Tensor, k: int, nprobe: int, node0: int = 0,
-                  nnodes: int | None = None):
+                  nnodes: int | None = None, R: int = 0):
         """Rows node0 .. node0 + nnodes - 1 of the IVFADC k-NN graph of the
-        added vectors xb (ids 0 .. ntotal - 1); a node is not its own neighbour."""
+        added vectors xb (ids 0 .. ntotal - 1); a node is not its own
+        neighbour.  R > 0 re-ranks an R-entry ADC short list exactly."""
         _dev(xb, torch.float32, "xb")
         if xb.dim() != 2 or xb.shape[1] != self.d or xb.shape[0] < self.ntotal:
             raise ValueError(f"xb must be the [ntotal, {self.d}] added vectors")
         nnodes = self.ntotal - node0 if nnodes is None else nnodes
         D = _out((nnodes, k), torch.float32, xb)
         I = _out((nnodes, k), torch.int64, xb)
-        _call("mk_ivfpq_knn_graph", self._h, _ptr(xb), node0, nnodes, k, nprobe, _ptr(D),
+        _call("mk_ivfpq_knn_graph", self._h, _ptr(xb), node0, nnodes, k, nprobe, R, _ptr(D),
               _ptr(I), _stream())
         return D, I
 
@@ -429,12 +480,26 @@ def profile_read(name: str):
 class MLP:
     """Probe-count predictor: din -> hidden (ReLU) -> hidden (ReLU) -> 1."""
 
-    def __init__(self, din: int, hidden: int, prec: str = "fp32"):
+    def __init__(self, din: int, hidden: int, prec: str = "fp32", _handle=None):
         self.din, self.hidden = din, hidden
-        h = _vp()
-        _call("mk_mlp_create", din, hidden, {"fp32": 0, "bf16": 1}[prec], ctypes.byref(h))
+        h = _handle
+        if h is None:
+            h = _vp()
+            _call("mk_mlp_create", din, hidden, {"fp32": 0, "bf16": 1}[prec], ctypes.byref(h))
         self._h = h
         self.n_params = int(lib().mk_mlp_num_params(h))
+
+    def save(self, path: str) -> None:
+        """Write parameters, Adam state and standardisation to `path`."""
+        _call("mk_mlp_save", self._h, os.fsencode(path))
+
+    @classmethod
+    def load(cls, path: str) -> "MLP":
+        h = _vp()
+        _call("mk_mlp_load", os.fsencode(path), ctypes.byref(h))
+        din, hidden, prec = _i32(), _i32(), _i32()
+        _call("mk_mlp_shape", h, ctypes.byref(din), ctypes.byref(hidden), ctypes.byref(prec))
+        return cls(din.value, hidden.value, {0: "fp32", 1: "bf16"}[prec.value], _handle=h)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -3,13 +3,14 @@
 // and the search: coarse exact search (Eq. 5), query tables of term 3, the
 // list scan with per-(query, list) lookup tables in LDS feeding WaveSelect,
 // and the merge of the per-list partial results (Eq. 6).
-#include <hipcub/hipcub.hpp>
+#include <hip/hip_fp16.h>
 
 #include <algorithm>
 #include <cstring>
 #include <vector>
 
 #include "common.hpp"
+#include "fileio.hpp"
 #include "kselect.hpp"
 #include "mlp.hpp"
 #include "profile.hpp"
@@ -29,6 +30,10 @@ struct mk_ivfpq {
     float* t1e = nullptr;           // [capacity] term 1 of Eq. 11 per entry
     int64_t* offsets_dev = nullptr; // [nlist + 1]
     std::vector<int64_t> offsets;   // host copy
+    // scan options: 16-bit lookup tables; probed lists per scan workgroup
+    // (0: chosen from the launch size, -1: all of a query's lists)
+    bool lut16 = false;
+    int32_t lists_per_group = 0;
 };
 
 namespace mk {
@@ -36,6 +41,16 @@ namespace mk {
 namespace {
 
 constexpr int kBlock = 256;
+// Element-wise kernels walk their items with a grid-stride loop; grids are
+// capped at kMaxBlocks so that no launch exceeds the 32-bit work-item count
+// of a grid dimension (a 50,000,000 x 128 array has 6.4e9 elements).
+constexpr int64_t kMaxBlocks = 1 << 20;
+#define kStride ((int64_t)gridDim.x * kBlock)
+
+unsigned grid_of(int64_t n) {
+    const int64_t b = ceil_div(n > 0 ? n : 1, kBlock);
+    return (unsigned)(b < kMaxBlocks ? b : kMaxBlocks);
+}
 
 void free_dev(void*& p) {
     if (p) (void)hipFree(p);
@@ -54,10 +69,10 @@ mk_status alloc_dev(T*& p, size_t count) {
 __global__ void gather_rows_kernel(const float* __restrict__ src, int32_t d,
                                    const int64_t* __restrict__ rows, int64_t n,
                                    float* __restrict__ dst) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= n * d) return;
-    const int64_t i = g / d, t = g % d;
-    dst[g] = src[rows[i] * d + t];
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n * d; g += kStride) {
+        const int64_t i = g / d, t = g % d;
+        dst[g] = src[rows[i] * d + t];
+    }
 }
 
 // Sum points into their centroid's FP64 accumulator (one thread per
@@ -65,24 +80,25 @@ __global__ void gather_rows_kernel(const float* __restrict__ src, int32_t d,
 __global__ void km_accumulate(const float* __restrict__ x, int64_t n, int32_t d,
                               const int64_t* __restrict__ assign, int32_t K,
                               double* __restrict__ sums, unsigned long long* __restrict__ counts) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= n * d) return;
-    const int64_t i = g / d, t = g % d;
-    const int64_t a = assign[i];
-    if (a < 0 || a >= K) return;  // invalid assignments are ignored
-    if (t == 0) atomicAdd(&counts[a], 1ull);
-    atomicAdd(&sums[a * d + t], (double)x[g]);
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n * d; g += kStride) {
+        const int64_t i = g / d, t = g % d;
+        const int64_t a = assign[i];
+        if (a < 0 || a >= K) continue;  // invalid assignments are ignored
+        if (t == 0) atomicAdd(&counts[a], 1ull);
+        atomicAdd(&sums[a * d + t], (double)x[g]);
+    }
 }
 
 __global__ void km_finalize(const double* __restrict__ sums,
                             const unsigned long long* __restrict__ counts, int32_t K, int32_t d,
                             float* __restrict__ c, int64_t* __restrict__ counts_out) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= (int64_t)K * d) return;
-    const int64_t j = g / d, t = g % d;
-    const unsigned long long n = counts[j];
-    if (n > 0) c[g] = (float)(sums[g] / (double)n);
-    if (t == 0) counts_out[j] = (int64_t)n;
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < (int64_t)K * d;
+         g += kStride) {
+        const int64_t j = g / d, t = g % d;
+        const unsigned long long n = counts[j];
+        if (n > 0) c[g] = (float)(sums[g] / (double)n);
+        if (t == 0) counts_out[j] = (int64_t)n;
+    }
 }
 
 // Empty clusters, in increasing index order, split the currently largest
@@ -160,11 +176,11 @@ mk_status kmeans_update(const float* x, int64_t n, int32_t d, const int64_t* ass
     MK_HIP(hipMemsetAsync(sums.ptr, 0, sizeof(double) * (size_t)K * d, s));
     MK_HIP(hipMemsetAsync(cnt.ptr, 0, sizeof(unsigned long long) * (size_t)K, s));
     if (n > 0) {
-        hipLaunchKernelGGL(km_accumulate, dim3((unsigned)ceil_div(n * d, kBlock)), dim3(kBlock), 0,
+        hipLaunchKernelGGL(km_accumulate, dim3(grid_of(n * d)), dim3(kBlock), 0,
                            s, x, n, d, assign, K, sums.as<double>(), cnt.as<unsigned long long>());
         MK_LAUNCHED();
     }
-    hipLaunchKernelGGL(km_finalize, dim3((unsigned)ceil_div((int64_t)K * d, kBlock)), dim3(kBlock),
+    hipLaunchKernelGGL(km_finalize, dim3(grid_of((int64_t)K * d)), dim3(kBlock),
                        0, s, sums.as<double>(), cnt.as<unsigned long long>(), K, d, c, counts);
     MK_LAUNCHED();
     hipLaunchKernelGGL(km_split_empty, dim3(1), dim3(kBlock), 0, s, c, counts, K, d);
@@ -279,36 +295,37 @@ mk_status pq_encode(const float* r, int64_t n, int32_t d, int32_t M, const float
 __global__ void residual_kernel(const float* __restrict__ x, int64_t n, int32_t d,
                                 const float* __restrict__ c, const int64_t* __restrict__ list,
                                 float* __restrict__ r) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= n * d) return;
-    const int64_t i = g / d, t = g % d;
-    r[g] = x[g] - c[list[i] * d + t];
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n * d; g += kStride) {
+        const int64_t i = g / d, t = g % d;
+        r[g] = x[g] - c[list[i] * d + t];
+    }
 }
 
 // dst[i, :] = src[i, off : off + w]
 __global__ void columns_kernel(const float* __restrict__ src, int64_t n, int32_t d, int32_t off,
                                int32_t w, float* __restrict__ dst) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= n * w) return;
-    const int64_t i = g / w, t = g % w;
-    dst[g] = src[i * d + off + t];
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n * w; g += kStride) {
+        const int64_t i = g / w, t = g % w;
+        dst[g] = src[i * d + off + t];
+    }
 }
 
 // term1[L, m, j] = ||c_{m,j}||^2 + 2 <c_L^m, c_{m,j}>   (Eq. 11, term 1)
 __global__ void term1_kernel(const float* __restrict__ coarse, const float* __restrict__ books,
                              int32_t nlist, int32_t M, int32_t ds, float* __restrict__ term1) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= (int64_t)nlist * M * 256) return;
-    const int64_t L = g / (M * 256);
-    const int32_t m = (int32_t)((g / 256) % M), j = (int32_t)(g % 256);
-    const float* cw = books + ((int64_t)m * 256 + j) * ds;
-    const float* cl = coarse + L * (int64_t)M * ds + (int64_t)m * ds;
-    float nn = 0.f, ip = 0.f;
-    for (int t = 0; t < ds; ++t) {
-        nn = fmaf(cw[t], cw[t], nn);
-        ip = fmaf(cl[t], cw[t], ip);
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < (int64_t)nlist * M * 256;
+         g += kStride) {
+        const int64_t L = g / (M * 256);
+        const int32_t m = (int32_t)((g / 256) % M), j = (int32_t)(g % 256);
+        const float* cw = books + ((int64_t)m * 256 + j) * ds;
+        const float* cl = coarse + L * (int64_t)M * ds + (int64_t)m * ds;
+        float nn = 0.f, ip = 0.f;
+        for (int t = 0; t < ds; ++t) {
+            nn = fmaf(cw[t], cw[t], nn);
+            ip = fmaf(cl[t], cw[t], ip);
+        }
+        term1[g] = fmaf(2.f, ip, nn);
     }
-    term1[g] = fmaf(2.f, ip, nn);
 }
 
 // term3[q, m, j] = <x_q^m, c_{m,j}>   (Eq. 11, term 3)
@@ -367,19 +384,96 @@ mk_status launch_term3(const float* xq, int64_t nq, int32_t M, int32_t ds, const
     return MK_OK;
 }
 
-__global__ void histogram_kernel(const int64_t* __restrict__ list, int64_t n,
-                                 unsigned long long* __restrict__ counts) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) atomicAdd(&counts[list[i]], 1ull);
+__global__ void fill_u32_kernel(unsigned int* __restrict__ a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += kStride) a[i] = 0u;
 }
 
-__global__ void to_key_kernel(const int64_t* __restrict__ list, int64_t n,
-                              uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) {
-        key[i] = (uint32_t)list[i];
-        val[i] = (uint32_t)i;
+// Stable placement of a batch into its lists without sorting.  The batch is
+// cut into chunks of kPlaceChunk entries, one wave each, walked 64 entries
+// at a time in batch order.  Within a group of 64 the lanes with equal lists
+// are found by repeated ballots on the first remaining lane's list; the
+// group's count for that list goes to the chunk's counter in one atomic.
+//   place_count: cnt[c][L] = entries of chunk c in list L
+//   place_prefix: per list, exclusive prefix over chunks (cnt[c][L] becomes
+//                 the list rank of chunk c's first entry) and the total
+//   place_new:   the same walk again; the atomic's old value plus the lane's
+//                rank among equal lanes below it is the entry's rank in its
+//                list among the batch, so entries keep batch order per list
+constexpr int64_t kPlaceChunk = 65536;
+
+template <bool PLACE>
+__device__ __forceinline__ void place_walk(const int64_t* __restrict__ list, int64_t nb,
+                                           int32_t nlist, unsigned int* __restrict__ cnt,
+                                           const int64_t* __restrict__ new_off,
+                                           const int64_t* __restrict__ old_off, int32_t M,
+                                           const uint8_t* __restrict__ batch_codes, int64_t id0,
+                                           uint8_t* __restrict__ codes, int64_t* __restrict__ ids) {
+    const int64_t c = blockIdx.x;
+    const int lane = threadIdx.x;
+    unsigned int* row = cnt + c * (int64_t)nlist;
+    const int64_t lo = c * kPlaceChunk;
+    const int64_t hi = lo + kPlaceChunk < nb ? lo + kPlaceChunk : nb;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t g = lo; g < hi; g += 64) {
+        const int64_t i = g + lane;
+        const bool ok = i < hi;
+        const int64_t L = ok ? list[i] : -1;
+        uint64_t todo = __ballot(ok);
+        int64_t rank = 0;
+        while (todo) {
+            const int first = __builtin_ctzll(todo);
+            const int64_t Lf = __shfl(L, first, 64);
+            const uint64_t same = __ballot(L == Lf) & todo;
+            unsigned int base = 0;
+            if (lane == first) {
+                if (PLACE)
+                    base = atomicAdd(&row[Lf], (unsigned int)__popcll(same));
+                else
+                    atomicAdd(&row[Lf], (unsigned int)__popcll(same));
+            }
+            if (PLACE) {
+                base = __shfl(base, first, 64);
+                if ((same >> lane) & 1ull) rank = (int64_t)base + __popcll(same & below);
+            }
+            todo &= ~same;
+        }
+        if (PLACE && ok) {
+            const int64_t pos = new_off[L] + (old_off[L + 1] - old_off[L]) + rank;
+            ids[pos] = id0 + i;
+            for (int m = 0; m < M; ++m) codes[pos * M + m] = batch_codes[i * M + m];
+        }
     }
+}
+
+__global__ __launch_bounds__(64) void place_count_kernel(const int64_t* __restrict__ list,
+                                                         int64_t nb, int32_t nlist,
+                                                         unsigned int* __restrict__ cnt) {
+    place_walk<false>(list, nb, nlist, cnt, nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr);
+}
+
+__global__ void place_prefix_kernel(unsigned int* __restrict__ cnt, int64_t nchunks,
+                                    int32_t nlist, unsigned long long* __restrict__ total) {
+    const int64_t L = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (L >= nlist) return;
+    unsigned long long run = 0;
+    for (int64_t c = 0; c < nchunks; ++c) {
+        const unsigned int v = cnt[c * nlist + L];
+        cnt[c * nlist + L] = (unsigned int)run;
+        run += v;
+    }
+    total[L] = run;
+}
+
+__global__ __launch_bounds__(64) void place_new_kernel(const int64_t* __restrict__ list,
+                                                       int64_t nb, int32_t nlist,
+                                                       unsigned int* __restrict__ cnt,
+                                                       const int64_t* __restrict__ new_off,
+                                                       const int64_t* __restrict__ old_off,
+                                                       int32_t M,
+                                                       const uint8_t* __restrict__ batch_codes,
+                                                       int64_t id0, uint8_t* __restrict__ codes,
+                                                       int64_t* __restrict__ ids) {
+    place_walk<true>(list, nb, nlist, cnt, new_off, old_off, M, batch_codes, id0, codes, ids);
 }
 
 // Old entries of list L move from old_off[L] + e to new_off[L] + e.
@@ -394,23 +488,6 @@ __global__ void move_old_kernel(const int64_t* __restrict__ old_off,
         ids[dst + e] = old_ids[lo + e];
         for (int m = 0; m < M; ++m) codes[(dst + e) * M + m] = old_codes[(lo + e) * M + m];
     }
-}
-
-// New entry p of the list-sorted batch (original row perm[p], list key[p])
-// goes after the list's old entries, in batch order.
-__global__ void place_new_kernel(const uint32_t* __restrict__ key, const uint32_t* __restrict__ perm,
-                                 int64_t nb, const int64_t* __restrict__ new_off,
-                                 const int64_t* __restrict__ old_off,
-                                 const int64_t* __restrict__ batch_off, int32_t M,
-                                 const uint8_t* __restrict__ batch_codes, int64_t id0,
-                                 uint8_t* __restrict__ codes, int64_t* __restrict__ ids) {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= nb) return;
-    const uint32_t L = key[p];
-    const int64_t i = perm[p];
-    const int64_t pos = new_off[L] + (old_off[L + 1] - old_off[L]) + (p - batch_off[L]);
-    ids[pos] = id0 + i;
-    for (int m = 0; m < M; ++m) codes[pos * M + m] = batch_codes[i * M + m];
 }
 
 // ---------------------------------------------------------------- list scan
@@ -429,11 +506,11 @@ __global__ void probe_features_kernel(const float* __restrict__ xq, int64_t nq, 
                                       const float* __restrict__ cd, int32_t ld,
                                       float* __restrict__ F) {
     const int32_t din = d + kProbeDists;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nq * din) return;
-    const int64_t q = e / din;
-    const int t = (int)(e % din);
-    F[e] = t < d ? xq[q * d + t] : cd[q * ld + (t - d)];
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nq * din; e += kStride) {
+        const int64_t q = e / din;
+        const int t = (int)(e % din);
+        F[e] = t < d ? xq[q * d + t] : cd[q * ld + (t - d)];
+    }
 }
 
 // list_of[id] = inverted list holding id.
@@ -465,30 +542,61 @@ __global__ void probe_labels_kernel(const int64_t* __restrict__ ci, int32_t ld, 
     if (label) label[q] = r;
 }
 
-__global__ void zero_first_kernel(int64_t* __restrict__ a) { a[0] = 0; }
-
-// Workgroups of the list scan per query: ceil(tau / G).
-__global__ void group_count_kernel(const int32_t* __restrict__ tau, int64_t nq, int32_t G,
-                                   int64_t* __restrict__ count) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < nq) count[q] = (tau[q] + G - 1) / G;
+// Per-query probe counts and the scan's work plan in one workgroup:
+// tau[q] = clamp(ceil(2^(yhat[q] + delta)), 1, cap) (also copied to `used`
+// when given), and the exclusive prefix sums of the per-query workgroup
+// counts ceil(tau / G): work[0] = 0, work[q + 1] = sum over q' <= q.
+// Queries go 1024 at a time; a wave prefix sum, then one over the 16 waves'
+// totals, then the running carry.
+__global__ __launch_bounds__(1024) void probe_plan_kernel(const float* __restrict__ yhat,
+                                                          int64_t nq, float delta, int32_t cap,
+                                                          int32_t G, int32_t* __restrict__ tau,
+                                                          int32_t* __restrict__ used,
+                                                          int64_t* __restrict__ work) {
+    __shared__ int64_t wsum[16];
+    __shared__ int64_t carry;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        carry = 0;
+        work[0] = 0;
+    }
+    __syncthreads();
+    for (int64_t base = 0; base < nq; base += 1024) {
+        const int64_t q = base + threadIdx.x;
+        int64_t x = 0;
+        if (q < nq) {
+            const float t = exp2f(yhat[q] + delta);
+            int32_t v = cap;
+            if (t < (float)cap) v = t <= 1.f ? 1 : (int32_t)ceilf(t);
+            tau[q] = v;
+            if (used) used[q] = v;
+            x = (v + G - 1) / G;
+        }
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        if (wave == 0) {
+            int64_t t = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                const int64_t y = __shfl_up(t, off, 64);
+                if (lane >= off) t += y;
+            }
+            if (lane < 16) wsum[lane] = t;
+        }
+        __syncthreads();
+        const int64_t incl = carry + (wave > 0 ? wsum[wave - 1] : 0) + x;
+        if (q < nq) work[q + 1] = incl;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = incl;
+        __syncthreads();
+    }
 }
 
-// tau = clamp(ceil(2^(yhat + delta)), 1, cap) per query; count[q] = tau.
-__global__ void probe_count_kernel(const float* __restrict__ yhat, int64_t nq, float delta,
-                                   int32_t cap, int32_t* __restrict__ tau,
-                                   int64_t* __restrict__ count) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq) return;
-    const float t = exp2f(yhat[q] + delta);
-    int32_t v = cap;
-    if (t < (float)cap) v = t <= 1.f ? 1 : (int32_t)ceilf(t);
-    tau[q] = v;
-    count[q] = v;
-}
-
-// Term 1 of Eq. 11 per list entry: the query-independent part of its ADC
-// distance, sum over sub-quantizers m of term1[L][m][code_m] (m in order).
 __global__ void entry_term1_kernel(const int64_t* __restrict__ offsets, int32_t M,
                                    const uint8_t* __restrict__ codes,
                                    const float* __restrict__ term1, float* __restrict__ t1e) {
@@ -513,7 +621,21 @@ __global__ void entry_term1_kernel(const int64_t* __restrict__ offsets, int32_t 
 // Item -> (query, group): fixed probe count nprobe (= ld) when work is null,
 // else query q owns items work[q] .. work[q + 1] - 1 and probes tau[q] lists.
 
-template <int KR>
+// Lookup-table entry types: FP32, or FP16 (half the LDS and half the bytes
+// per gather; each entry rounded once, sums still in FP32).
+template <bool H16> struct LutT;
+template <> struct LutT<false> {
+    typedef float type;
+    static __device__ __forceinline__ float make(float v) { return v; }
+    static __device__ __forceinline__ float get(float v) { return v; }
+};
+template <> struct LutT<true> {
+    typedef __half type;
+    static __device__ __forceinline__ __half make(float v) { return __float2half_rn(v); }
+    static __device__ __forceinline__ float get(__half v) { return __half2float(v); }
+};
+
+template <int KR, bool H16>
 __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
     const float* __restrict__ term3, const float* __restrict__ t1e,
     const float* __restrict__ coarse_d, const int64_t* __restrict__ coarse_i, int32_t ld,
@@ -522,9 +644,11 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
     uint64_t* __restrict__ part, const int64_t* __restrict__ work,
     const int32_t* __restrict__ tau, int64_t nq, int64_t excl_base) {
     constexpr int T = SelParams<KR>::T;
+    typedef LutT<H16> LT;
+    typedef typename LT::type lut_t;
     extern __shared__ __align__(16) unsigned char smem[];
-    float* lut = reinterpret_cast<float*>(smem);
-    uint64_t* qbuf = reinterpret_cast<uint64_t*>(smem + (size_t)M * 256 * sizeof(float));
+    lut_t* lut = reinterpret_cast<lut_t*>(smem);
+    uint64_t* qbuf = reinterpret_cast<uint64_t*>(smem + (size_t)M * 256 * sizeof(lut_t));
 
     const int64_t item = blockIdx.x;
     int64_t q, g;
@@ -555,7 +679,7 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
     const int64_t excl = excl_base >= 0 ? excl_base + q : -1;
 
     const float* t3 = term3 + q * (int64_t)M * 256;
-    for (int e = threadIdx.x; e < M * 256; e += 64 * kScanWaves) lut[e] = -2.f * t3[e];
+    for (int e = threadIdx.x; e < M * 256; e += 64 * kScanWaves) lut[e] = LT::make(-2.f * t3[e]);
     __syncthreads();
 
     WaveSelect<KR, T> ws;
@@ -590,7 +714,7 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
 #pragma unroll
                             for (int b = 0; b < 4; ++b) {
                                 const int m = m0 + 4 * h + b;
-                                dist += lut[m * 256 + ((ww[h] >> (8 * b)) & 0xFF)];
+                                dist += LT::get(lut[m * 256 + ((ww[h] >> (8 * b)) & 0xFF)]);
                             }
                         }
                     }
@@ -598,7 +722,8 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
                     for (int m0 = 0; m0 < M; m0 += 4) {
                         const uint32_t w = *reinterpret_cast<const uint32_t*>(c + m0);
 #pragma unroll
-                        for (int b = 0; b < 4; ++b) dist += lut[(m0 + b) * 256 + ((w >> (8 * b)) & 0xFF)];
+                        for (int b = 0; b < 4; ++b)
+                            dist += LT::get(lut[(m0 + b) * 256 + ((w >> (8 * b)) & 0xFF)]);
                     }
                 }
             }
@@ -647,22 +772,37 @@ int32_t scan_group(int64_t total_probes) {
     return (int32_t)(g < 1 ? 1 : g > 16 ? 16 : g);
 }
 
+// The index's choice of lists per workgroup for nq queries probing up to
+// nprobe lists each: automatic (scan_group), all of a query's lists in one
+// workgroup (the per-query fused scan), or a fixed count.
+int32_t scan_group_of(const mk_ivfpq* ix, int64_t nq, int32_t nprobe, int32_t auto_probes) {
+    if (ix->lists_per_group < 0) return nprobe;
+    if (ix->lists_per_group > 0) return ix->lists_per_group < nprobe ? ix->lists_per_group : nprobe;
+    return scan_group(nq * (int64_t)auto_probes);
+}
+
 mk_status launch_scan(const float* term3, const float* t1e, const float* cd, const int64_t* ci,
                       int32_t ld, const int64_t* offsets, const uint8_t* codes,
                       const int64_t* ids, int32_t M, int64_t nq, int32_t G, int32_t k,
                       uint64_t* part, int64_t items, hipStream_t s,
                       const int64_t* work = nullptr, const int32_t* tau = nullptr,
-                      int64_t excl_base = -1) {
+                      int64_t excl_base = -1, bool lut16 = false) {
     if (items == 0) return MK_OK;
-    MK_REQUIRE(items < (1ll << 31), MK_ERR_UNSUPPORTED, "too many scan items for one launch");
-    const size_t shm = (size_t)M * 256 * sizeof(float) + (size_t)kScanWaves * k * sizeof(uint64_t);
+    MK_REQUIRE(items * 64 * kScanWaves < (1ll << 32), MK_ERR_UNSUPPORTED,
+               "too many scan workgroups for one launch (search fewer queries per call)");
+    const size_t shm = (size_t)M * 256 * (lut16 ? 2 : 4) + (size_t)kScanWaves * k * sizeof(uint64_t);
     MK_REQUIRE(shm <= 65536, MK_ERR_UNSUPPORTED,
-               "lookup tables plus merge buffers exceed 64 KiB of LDS (reduce M or k)");
+               "lookup tables plus merge buffers exceed 64 KiB of LDS (reduce M or k, or use "
+               "16-bit tables)");
     const dim3 grid((unsigned)items), block(64 * kScanWaves);
-    ProfScope prof("ivf_scan", s);
+    ProfScope prof(lut16 ? "ivf_scan_lut16" : "ivf_scan", s);
 #define MK_SCAN(KR)                                                                          \
-    hipLaunchKernelGGL(ivf_scan<KR>, grid, block, shm, s, term3, t1e, cd, ci, ld, offsets,  \
-                       codes, ids, M, G, k, part, work, tau, nq, excl_base)
+    if (lut16)                                                                               \
+        hipLaunchKernelGGL((ivf_scan<KR, true>), grid, block, shm, s, term3, t1e, cd, ci, ld, \
+                           offsets, codes, ids, M, G, k, part, work, tau, nq, excl_base);    \
+    else                                                                                     \
+        hipLaunchKernelGGL((ivf_scan<KR, false>), grid, block, shm, s, term3, t1e, cd, ci,   \
+                           ld, offsets, codes, ids, M, G, k, part, work, tau, nq, excl_base)
     switch (queue_regs(k)) {
         case 1: MK_SCAN(1); break;
         case 2: MK_SCAN(2); break;
@@ -675,7 +815,6 @@ mk_status launch_scan(const float* term3, const float* t1e, const float* cd, con
     return MK_OK;
 }
 
-unsigned grid_of(int64_t n) { return (unsigned)ceil_div(n > 0 ? n : 1, kBlock); }
 
 mk_status build_term1(mk_ivfpq* ix, hipStream_t s) {
     free_dev(reinterpret_cast<void*&>(ix->term1));
@@ -753,7 +892,7 @@ mk_status train(mk_ivfpq* ix, const float* xt, int64_t nt, int32_t niter,
 mk_status add(mk_ivfpq* ix, const float* xb, int64_t nb, hipStream_t s) {
     const int32_t d = ix->d, nlist = ix->nlist, M = ix->M;
     if (nb == 0) return MK_OK;
-    Scratch list, res, bcodes, cnt, keys, vals, keys2, vals2, tmp, oldoff, newoff, boff;
+    Scratch list, res, bcodes, cnt, tot, oldoff, newoff;
     MK_TRY(list.alloc(sizeof(int64_t) * nb, s));
     MK_TRY(res.alloc(sizeof(float) * nb * d, s));
     MK_TRY(bcodes.alloc((size_t)nb * M, s));
@@ -762,40 +901,28 @@ mk_status add(mk_ivfpq* ix, const float* xb, int64_t nb, hipStream_t s) {
                        ix->coarse, list.as<int64_t>(), res.as<float>());
     MK_LAUNCHED();
     MK_TRY(pq_encode(res.as<float>(), nb, d, M, ix->books, bcodes.as<uint8_t>(), s));
-    // per-list counts of the batch
-    MK_TRY(cnt.alloc(sizeof(unsigned long long) * nlist, s));
-    MK_HIP(hipMemsetAsync(cnt.ptr, 0, sizeof(unsigned long long) * nlist, s));
-    hipLaunchKernelGGL(histogram_kernel, dim3(grid_of(nb)), dim3(kBlock), 0, s,
-                       list.as<int64_t>(), nb, cnt.as<unsigned long long>());
+    // per-chunk, per-list counts of the batch, their prefix over chunks and
+    // the per-list totals
+    const int64_t nchunks = ceil_div(nb, kPlaceChunk);
+    MK_TRY(cnt.alloc(sizeof(unsigned int) * (size_t)nchunks * nlist, s));
+    MK_TRY(tot.alloc(sizeof(unsigned long long) * nlist, s));
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_of(nchunks * nlist)), dim3(kBlock), 0, s,
+                       cnt.as<unsigned int>(), nchunks * nlist);
+    MK_LAUNCHED();
+    hipLaunchKernelGGL(place_count_kernel, dim3((unsigned)nchunks), dim3(64), 0, s,
+                       list.as<int64_t>(), nb, nlist, cnt.as<unsigned int>());
+    MK_LAUNCHED();
+    hipLaunchKernelGGL(place_prefix_kernel, dim3(grid_of(nlist)), dim3(kBlock), 0, s,
+                       cnt.as<unsigned int>(), nchunks, nlist, tot.as<unsigned long long>());
     MK_LAUNCHED();
     std::vector<unsigned long long> hc(nlist);
-    MK_HIP(hipMemcpyAsync(hc.data(), cnt.ptr, sizeof(unsigned long long) * nlist,
+    MK_HIP(hipMemcpyAsync(hc.data(), tot.ptr, sizeof(unsigned long long) * nlist,
                           hipMemcpyDeviceToHost, s));
-    // stable order of the batch by list (radix sort is stable)
-    MK_TRY(keys.alloc(sizeof(uint32_t) * nb, s));
-    MK_TRY(vals.alloc(sizeof(uint32_t) * nb, s));
-    MK_TRY(keys2.alloc(sizeof(uint32_t) * nb, s));
-    MK_TRY(vals2.alloc(sizeof(uint32_t) * nb, s));
-    hipLaunchKernelGGL(to_key_kernel, dim3(grid_of(nb)), dim3(kBlock), 0, s, list.as<int64_t>(),
-                       nb, keys.as<uint32_t>(), vals.as<uint32_t>());
-    MK_LAUNCHED();
-    int end_bit = 1;
-    while ((1ll << end_bit) < nlist) ++end_bit;
-    size_t tmp_bytes = 0;
-    MK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys.as<uint32_t>(),
-                                              keys2.as<uint32_t>(), vals.as<uint32_t>(),
-                                              vals2.as<uint32_t>(), (int)nb, 0, end_bit, s));
-    MK_TRY(tmp.alloc(tmp_bytes, s));
-    MK_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.ptr, tmp_bytes, keys.as<uint32_t>(),
-                                              keys2.as<uint32_t>(), vals.as<uint32_t>(),
-                                              vals2.as<uint32_t>(), (int)nb, 0, end_bit, s));
     MK_HIP(hipStreamSynchronize(s));
     // new CSR offsets (host bookkeeping of nlist + 1 integers)
-    std::vector<int64_t> bo(nlist + 1, 0), no(nlist + 1, 0);
-    for (int32_t L = 0; L < nlist; ++L) {
-        bo[L + 1] = bo[L] + (int64_t)hc[L];
+    std::vector<int64_t> no(nlist + 1, 0);
+    for (int32_t L = 0; L < nlist; ++L)
         no[L + 1] = no[L] + (ix->offsets[L + 1] - ix->offsets[L]) + (int64_t)hc[L];
-    }
     const int64_t total = no[nlist];
     MK_REQUIRE(total < (1ll << 32) - 1, MK_ERR_UNSUPPORTED, "an index holds fewer than 2^32 - 1 vectors");
     uint8_t* ncodes = nullptr;
@@ -804,21 +931,18 @@ mk_status add(mk_ivfpq* ix, const float* xb, int64_t nb, hipStream_t s) {
     MK_TRY(alloc_dev(nids, (size_t)total));
     MK_TRY(oldoff.alloc(sizeof(int64_t) * (nlist + 1), s));
     MK_TRY(newoff.alloc(sizeof(int64_t) * (nlist + 1), s));
-    MK_TRY(boff.alloc(sizeof(int64_t) * (nlist + 1), s));
     MK_HIP(hipMemcpyAsync(oldoff.ptr, ix->offsets.data(), sizeof(int64_t) * (nlist + 1),
                           hipMemcpyHostToDevice, s));
     MK_HIP(hipMemcpyAsync(newoff.ptr, no.data(), sizeof(int64_t) * (nlist + 1),
-                          hipMemcpyHostToDevice, s));
-    MK_HIP(hipMemcpyAsync(boff.ptr, bo.data(), sizeof(int64_t) * (nlist + 1),
                           hipMemcpyHostToDevice, s));
     if (ix->ntotal > 0) {
         hipLaunchKernelGGL(move_old_kernel, dim3(nlist), dim3(kBlock), 0, s, oldoff.as<int64_t>(),
                            newoff.as<int64_t>(), M, ix->codes, ix->ids, ncodes, nids);
         MK_LAUNCHED();
     }
-    hipLaunchKernelGGL(place_new_kernel, dim3(grid_of(nb)), dim3(kBlock), 0, s,
-                       keys2.as<uint32_t>(), vals2.as<uint32_t>(), nb, newoff.as<int64_t>(),
-                       oldoff.as<int64_t>(), boff.as<int64_t>(), M, bcodes.as<uint8_t>(),
+    hipLaunchKernelGGL(place_new_kernel, dim3((unsigned)nchunks), dim3(64), 0, s,
+                       list.as<int64_t>(), nb, nlist, cnt.as<unsigned int>(),
+                       newoff.as<int64_t>(), oldoff.as<int64_t>(), M, bcodes.as<uint8_t>(),
                        ix->ntotal, ncodes, nids);
     MK_LAUNCHED();
     MK_HIP(hipStreamSynchronize(s));
@@ -850,7 +974,7 @@ mk_status scan_fixed(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t nprobe, 
     MK_TRY(cd.alloc(sizeof(float) * nq * nprobe, s));
     MK_TRY(ci.alloc(sizeof(int64_t) * nq * nprobe, s));
     MK_TRY(t3.alloc(sizeof(float) * nq * M * 256, s));
-    const int32_t G = scan_group(nq * nprobe);
+    const int32_t G = scan_group_of(ix, nq, nprobe, nprobe);
     *ngroups = ceil_div(nprobe, G);
     MK_TRY(part.alloc(sizeof(uint64_t) * nq * *ngroups * kk, s));
     MK_TRY(knn_search(xq, nq, ix->coarse, ix->coarse_norms, ix->nlist, ix->d, nprobe,
@@ -861,7 +985,7 @@ mk_status scan_fixed(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t nprobe, 
     }
     return launch_scan(t3.as<float>(), ix->t1e, cd.as<float>(), ci.as<int64_t>(), nprobe,
                        ix->offsets_dev, ix->codes, ix->ids, M, nq, G, kk, part.as<uint64_t>(),
-                       nq * *ngroups, s, nullptr, nullptr, excl_base);
+                       nq * *ngroups, s, nullptr, nullptr, excl_base, ix->lut16);
 }
 
 mk_status search(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t k, int32_t nprobe, float* D,
@@ -876,10 +1000,11 @@ mk_status search(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t k, int32_t n
 // IVFADC short list of R entries per query, then exact re-ranking of that
 // list against the full-precision database rows (row id of xb = vector id).
 mk_status search_rerank(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t k, int32_t nprobe,
-                        int32_t R, const float* xb, float* D, int64_t* I, hipStream_t s) {
+                        int32_t R, const float* xb, float* D, int64_t* I, hipStream_t s,
+                        int64_t excl_base = -1) {
     Scratch part, keys;
     int64_t ng = 0;
-    MK_TRY(scan_fixed(ix, xq, nq, nprobe, R, part, &ng, s));
+    MK_TRY(scan_fixed(ix, xq, nq, nprobe, R, part, &ng, s, excl_base));
     MK_TRY(keys.alloc(sizeof(uint64_t) * nq * 64 * queue_regs(R), s));
     {
         ProfScope prof("ivf_merge", s);
@@ -929,13 +1054,12 @@ mk_status search_learned(mk_ivfpq* ix, const mk_mlp* net, float delta, const flo
                          float* D, int64_t* I, int32_t* used, hipStream_t s) {
     const int32_t M = ix->M;
     const int32_t kk = R > 0 ? R : k;
-    Scratch cd, ci, F, yhat, tau, cnt, work, tmp, t3, part, keys;
+    Scratch cd, ci, F, yhat, tau, work, t3, part, keys;
     MK_TRY(cd.alloc(sizeof(float) * nq * cap, s));
     MK_TRY(ci.alloc(sizeof(int64_t) * nq * cap, s));
     MK_TRY(F.alloc(sizeof(float) * nq * (ix->d + kProbeDists), s));
     MK_TRY(yhat.alloc(sizeof(float) * nq, s));
     MK_TRY(tau.alloc(sizeof(int32_t) * nq, s));
-    MK_TRY(cnt.alloc(sizeof(int64_t) * nq, s));
     MK_TRY(work.alloc(sizeof(int64_t) * (nq + 1), s));
     // coarse order up to cap probes; its first kProbeDists distances are the
     // network's distance features
@@ -949,28 +1073,14 @@ mk_status search_learned(mk_ivfpq* ix, const mk_mlp* net, float delta, const flo
         ProfScope prof("mlp_forward", s);
         MK_TRY(mlp_forward_dev(net, F.as<float>(), nq, yhat.as<float>(), s));
     }
-    hipLaunchKernelGGL(probe_count_kernel, dim3(grid_of(nq)), dim3(kBlock), 0, s,
-                       yhat.as<float>(), nq, delta, cap, tau.as<int32_t>(), cnt.as<int64_t>());
-    MK_LAUNCHED();
-    if (used)
-        MK_HIP(hipMemcpyAsync(used, tau.ptr, sizeof(int32_t) * nq, hipMemcpyDeviceToDevice, s));
-    // workgroups per query ceil(tau / G) and their exclusive prefix sums
-    // work[0] = 0, work[q + 1] = cnt[0] + ... + cnt[q], all on the device; the
-    // scan grid is sized for tau = cap everywhere and the surplus workgroups
-    // return at once, so the search never waits for the host
-    const int32_t G = scan_group(nq * (int64_t)(cap < 8 ? cap : 8));
+    // probe counts and the scan's work plan on the device: the scan grid is
+    // sized for tau = cap everywhere and the surplus workgroups return at
+    // once, so the search never waits for the host
+    const int32_t G = scan_group_of(ix, nq, cap, cap < 8 ? cap : 8);
     const int64_t max_items = nq * ceil_div(cap, G);
-    hipLaunchKernelGGL(group_count_kernel, dim3(grid_of(nq)), dim3(kBlock), 0, s,
-                       tau.as<int32_t>(), nq, G, cnt.as<int64_t>());
+    hipLaunchKernelGGL(probe_plan_kernel, dim3(1), dim3(1024), 0, s, yhat.as<float>(), nq, delta,
+                       cap, G, tau.as<int32_t>(), used, work.as<int64_t>());
     MK_LAUNCHED();
-    hipLaunchKernelGGL(zero_first_kernel, dim3(1), dim3(1), 0, s, work.as<int64_t>());
-    MK_LAUNCHED();
-    size_t tmp_bytes = 0;
-    MK_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, cnt.as<int64_t>(),
-                                            work.as<int64_t>() + 1, (int)nq, s));
-    MK_TRY(tmp.alloc(tmp_bytes, s));
-    MK_HIP(hipcub::DeviceScan::InclusiveSum(tmp.ptr, tmp_bytes, cnt.as<int64_t>(),
-                                            work.as<int64_t>() + 1, (int)nq, s));
     MK_TRY(t3.alloc(sizeof(float) * nq * M * 256, s));
     MK_TRY(part.alloc(sizeof(uint64_t) * max_items * kk, s));
     {
@@ -979,7 +1089,7 @@ mk_status search_learned(mk_ivfpq* ix, const mk_mlp* net, float delta, const flo
     }
     MK_TRY(launch_scan(t3.as<float>(), ix->t1e, cd.as<float>(), ci.as<int64_t>(), cap,
                        ix->offsets_dev, ix->codes, ix->ids, M, nq, G, kk, part.as<uint64_t>(),
-                       max_items, s, work.as<int64_t>(), tau.as<int32_t>()));
+                       max_items, s, work.as<int64_t>(), tau.as<int32_t>(), -1, ix->lut16));
     if (R <= 0) {
         ProfScope prof("ivf_merge", s);
         return merge_key_lists(part.as<uint64_t>(), nq, 0, k, D, I, s, nullptr,
@@ -1028,8 +1138,8 @@ extern "C" mk_status mk_ivfpq_create(int32_t d, int32_t nlist, int32_t M, mk_ivf
     MK_REQUIRE(out, MK_ERR_INVALID_ARG, "null output pointer");
     MK_REQUIRE(d >= 1 && d <= 256, MK_ERR_UNSUPPORTED, "d must be in [1, 256]");
     MK_REQUIRE(nlist >= 1 && nlist <= (1 << 24), MK_ERR_INVALID_ARG, "nlist must be in [1, 2^24]");
-    MK_REQUIRE(M >= 4 && M <= 64 && M % 4 == 0, MK_ERR_UNSUPPORTED,
-               "M must be a multiple of 4 in [4, 64]");
+    MK_REQUIRE(M >= 4 && M <= 128 && M % 4 == 0, MK_ERR_UNSUPPORTED,
+               "M must be a multiple of 4 in [4, 128]");
     MK_REQUIRE(d % M == 0, MK_ERR_INVALID_ARG, "d must be a multiple of M");
     mk_ivfpq* ix = new (std::nothrow) mk_ivfpq();
     MK_REQUIRE(ix, MK_ERR_OOM, "host allocation failed");
@@ -1099,8 +1209,8 @@ extern "C" mk_status mk_ivfpq_search(mk_ivfpq* ix, const float* xq, int64_t nq, 
 }
 
 extern "C" mk_status mk_ivfpq_knn_graph(mk_ivfpq* ix, const float* xb, int64_t node0,
-                                        int64_t nnodes, int32_t k, int32_t nprobe, float* D,
-                                        int64_t* I, mk_stream_t stream) {
+                                        int64_t nnodes, int32_t k, int32_t nprobe, int32_t R,
+                                        float* D, int64_t* I, mk_stream_t stream) {
     MK_REQUIRE(ix, MK_ERR_INVALID_ARG, "null index");
     MK_REQUIRE(ix->trained, MK_ERR_STATE, "index is not trained");
     MK_REQUIRE(node0 >= 0 && nnodes >= 0 && node0 + nnodes <= ix->ntotal, MK_ERR_INVALID_ARG,
@@ -1109,6 +1219,8 @@ extern "C" mk_status mk_ivfpq_knn_graph(mk_ivfpq* ix, const float* xb, int64_t n
     MK_REQUIRE(k <= mk::kMaxK, MK_ERR_UNSUPPORTED, "k must be <= 1024");
     MK_REQUIRE(nprobe >= 1 && nprobe <= ix->nlist && nprobe <= mk::kMaxK, MK_ERR_INVALID_ARG,
                "need 1 <= nprobe <= min(nlist, 1024)");
+    MK_REQUIRE(R == 0 || (R >= k && R <= mk::kMaxK), MK_ERR_INVALID_ARG,
+               "R must be 0 (no re-rank) or in [k, 1024]");
     if (nnodes == 0) return MK_OK;
     MK_REQUIRE(xb && D && I, MK_ERR_INVALID_ARG, "null pointer");
     const hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1117,7 +1229,11 @@ extern "C" mk_status mk_ivfpq_knn_graph(mk_ivfpq* ix, const float* xb, int64_t n
     for (int64_t b = 0; b < nnodes; b += kBatch) {
         const int64_t n = nnodes - b < kBatch ? nnodes - b : kBatch;
         const int64_t first = node0 + b;
-        MK_TRY(mk::search(ix, xb + first * ix->d, n, k, nprobe, D + b * k, I + b * k, s, first));
+        const float* xq = xb + first * ix->d;
+        if (R > 0)
+            MK_TRY(mk::search_rerank(ix, xq, n, k, nprobe, R, xb, D + b * k, I + b * k, s, first));
+        else
+            MK_TRY(mk::search(ix, xq, n, k, nprobe, D + b * k, I + b * k, s, first));
     }
     return MK_OK;
 }
@@ -1189,7 +1305,27 @@ extern "C" mk_status mk_ivfpq_search_learned(mk_ivfpq* ix, const mk_mlp* net, fl
                               static_cast<hipStream_t>(stream));
 }
 
+extern "C" mk_status mk_ivfpq_set_scan_options(mk_ivfpq* ix, mk_precision lut_precision,
+                                               int32_t lists_per_group) {
+    MK_REQUIRE(ix, MK_ERR_INVALID_ARG, "null index");
+    MK_REQUIRE(lut_precision == MK_PREC_FP32 || lut_precision == MK_PREC_FP16, MK_ERR_UNSUPPORTED,
+               "lookup tables are FP32 or FP16");
+    MK_REQUIRE(lists_per_group >= -1 && lists_per_group <= mk::kMaxK, MK_ERR_INVALID_ARG,
+               "lists_per_group must be -1, 0 or a count up to 1024");
+    ix->lut16 = lut_precision == MK_PREC_FP16;
+    ix->lists_per_group = lists_per_group;
+    return MK_OK;
+}
+
 extern "C" int32_t mk_ivfpq_dim(const mk_ivfpq* ix) { return ix ? ix->d : 0; }
+
+extern "C" mk_status mk_ivfpq_shape(const mk_ivfpq* ix, int32_t* d, int32_t* nlist, int32_t* M) {
+    MK_REQUIRE(ix, MK_ERR_INVALID_ARG, "null index");
+    if (d) *d = ix->d;
+    if (nlist) *nlist = ix->nlist;
+    if (M) *M = ix->M;
+    return MK_OK;
+}
 
 extern "C" mk_status mk_ivfpq_search_workspace_bytes(const mk_ivfpq* ix, int64_t nq, int32_t k,
                                                      int32_t nprobe, int32_t R, size_t* bytes) {
@@ -1252,5 +1388,94 @@ extern "C" mk_status mk_ivfpq_get_lists(const mk_ivfpq* ix, int64_t* offsets, ui
         MK_HIP(hipMemcpy(codes, ix->codes, (size_t)ix->ntotal * ix->M, hipMemcpyDeviceToHost));
     if (ids && ix->ntotal)
         MK_HIP(hipMemcpy(ids, ix->ids, sizeof(int64_t) * ix->ntotal, hipMemcpyDeviceToHost));
+    return MK_OK;
+}
+
+// ---------------------------------------------------------------- save / load
+namespace mk {
+namespace {
+constexpr char kIndexMagic[8] = {'M', 'K', 'I', 'V', 'F', 'P', 'Q', '\0'};
+constexpr uint32_t kIndexVersion = 1;
+
+// Fills a freshly created index from the body of an index file (after the
+// header) and rebuilds the derived tables with the same kernels as
+// train/add, so searches after a load equal searches before the save.
+mk_status load_body(mk_ivfpq* ix, BinFile& f, int64_t ntotal, hipStream_t s) {
+    const int32_t nlist = ix->nlist, M = ix->M;
+    MK_TRY(alloc_quantizers(ix));
+    MK_TRY(get_device(f, ix->coarse, sizeof(float) * (size_t)nlist * ix->d));
+    MK_TRY(get_device(f, ix->books, sizeof(float) * (size_t)M * 256 * ix->dsub));
+    std::vector<int64_t> offs(nlist + 1);
+    MK_REQUIRE(f.get(offs.data(), sizeof(int64_t) * offs.size()), MK_ERR_INVALID_ARG,
+               f.path + " is truncated");
+    MK_REQUIRE(offs[0] == 0 && offs[nlist] == ntotal, MK_ERR_INVALID_ARG,
+               f.path + ": list offsets do not span the stored entries");
+    for (int32_t L = 0; L < nlist; ++L)
+        MK_REQUIRE(offs[L + 1] >= offs[L], MK_ERR_INVALID_ARG, f.path + ": list offsets decrease");
+    MK_TRY(alloc_dev(ix->codes, (size_t)ntotal * M));
+    MK_TRY(alloc_dev(ix->ids, (size_t)ntotal));
+    MK_TRY(get_device(f, ix->codes, (size_t)ntotal * M));
+    MK_TRY(get_device(f, ix->ids, sizeof(int64_t) * (size_t)ntotal));
+    MK_REQUIRE(f.at_end(), MK_ERR_INVALID_ARG, f.path + " has trailing bytes");
+    MK_TRY(build_term1(ix, s));
+    ix->offsets = offs;
+    ix->ntotal = ntotal;
+    ix->capacity = ntotal;
+    MK_TRY(upload_offsets(ix, s));
+    MK_TRY(alloc_dev(ix->t1e, (size_t)(ntotal > 0 ? ntotal : 1)));
+    hipLaunchKernelGGL(entry_term1_kernel, dim3(nlist), dim3(kBlock), 0, s, ix->offsets_dev, M,
+                       ix->codes, ix->term1, ix->t1e);
+    MK_LAUNCHED();
+    MK_HIP(hipStreamSynchronize(s));
+    ix->trained = true;
+    return MK_OK;
+}
+}  // namespace
+}  // namespace mk
+
+extern "C" mk_status mk_ivfpq_save(const mk_ivfpq* ix, const char* path) {
+    MK_REQUIRE(ix && path, MK_ERR_INVALID_ARG, "null pointer");
+    MK_REQUIRE(ix->trained, MK_ERR_STATE, "index is not trained");
+    MK_HIP(hipDeviceSynchronize());
+    mk::BinFile f(path, "wb");
+    MK_REQUIRE(f.ok(), MK_ERR_INVALID_ARG, std::string("cannot open ") + path + " for writing");
+    const bool head = f.put(mk::kIndexMagic, 8) && f.put_v(mk::kIndexVersion) && f.put_v(ix->d) &&
+                      f.put_v(ix->nlist) && f.put_v(ix->M) && f.put_v(ix->ntotal);
+    MK_REQUIRE(head, MK_ERR_INVALID_ARG, std::string("write to ") + path + " failed");
+    MK_TRY(mk::put_device(f, ix->coarse, sizeof(float) * (size_t)ix->nlist * ix->d));
+    MK_TRY(mk::put_device(f, ix->books, sizeof(float) * (size_t)ix->M * 256 * ix->dsub));
+    MK_REQUIRE(f.put(ix->offsets.data(), sizeof(int64_t) * (ix->nlist + 1)), MK_ERR_INVALID_ARG,
+               std::string("write to ") + path + " failed");
+    MK_TRY(mk::put_device(f, ix->codes, (size_t)ix->ntotal * ix->M));
+    MK_TRY(mk::put_device(f, ix->ids, sizeof(int64_t) * (size_t)ix->ntotal));
+    MK_REQUIRE(f.close(), MK_ERR_INVALID_ARG, std::string("write to ") + path + " failed");
+    return MK_OK;
+}
+
+extern "C" mk_status mk_ivfpq_load(const char* path, mk_ivfpq** out) {
+    MK_REQUIRE(path && out, MK_ERR_INVALID_ARG, "null pointer");
+    *out = nullptr;
+    mk::BinFile f(path, "rb");
+    MK_REQUIRE(f.ok(), MK_ERR_INVALID_ARG, std::string("cannot open ") + path);
+    char magic[8];
+    uint32_t version = 0;
+    int32_t d = 0, nlist = 0, M = 0;
+    int64_t ntotal = 0;
+    const bool head = f.get(magic, 8) && f.get_v(version) && f.get_v(d) && f.get_v(nlist) &&
+                      f.get_v(M) && f.get_v(ntotal);
+    MK_REQUIRE(head && std::memcmp(magic, mk::kIndexMagic, 8) == 0, MK_ERR_INVALID_ARG,
+               std::string(path) + " is not an IVFPQ index file");
+    MK_REQUIRE(version == mk::kIndexVersion, MK_ERR_UNSUPPORTED,
+               std::string(path) + ": unknown index file version");
+    MK_REQUIRE(ntotal >= 0 && ntotal < 0xFFFFFFFFll, MK_ERR_INVALID_ARG,
+               std::string(path) + ": bad entry count");
+    mk_ivfpq* ix = nullptr;
+    MK_TRY(mk_ivfpq_create(d, nlist, M, &ix));
+    const mk_status st = mk::load_body(ix, f, ntotal, nullptr);
+    if (st != MK_OK) {
+        mk_ivfpq_destroy(ix);
+        return st;
+    }
+    *out = ix;
     return MK_OK;
 }

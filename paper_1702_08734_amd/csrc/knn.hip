@@ -18,6 +18,7 @@
 //      and re-ranks them.  The selection keeps k + 16 candidates (when the
 //      1024-entry queue allows) so that the FP32 cancellation of the norm
 //      decomposition cannot push a true neighbour out of the final k.
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -153,6 +154,21 @@ __global__ void drop_node_kernel(const float* __restrict__ D1, const int64_t* __
     }
 }
 
+// Chunk c's exact results (D, I local to the chunk) as merge keys in
+// keys[q][c][k]: (distance, global row) for L2, (-product, global row) for
+// inner products; padding entries (I = -1) become sentinels.
+__global__ void chunk_keys_kernel(const float* __restrict__ D, const int64_t* __restrict__ I,
+                                  int64_t nq, int32_t k, int32_t c, int32_t nchunks,
+                                  int64_t row0, int32_t largest, uint64_t* __restrict__ keys) {
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < nq * k;
+         g += (int64_t)gridDim.x * 256) {
+        const int64_t q = g / k, j = g % k;
+        const int64_t i = I[g];
+        keys[(q * nchunks + c) * k + j] =
+            i < 0 ? kSentinel : make_key(largest ? -D[g] : D[g], (uint32_t)(row0 + i));
+    }
+}
+
 template <int KR>
 mk_status rerank_launch(const uint64_t* keys, int64_t nq, int32_t R, const float* xq,
                         const float* xb, int32_t d, bool l2, bool vec, int32_t k, float* D,
@@ -279,6 +295,106 @@ extern "C" mk_status mk_knn_graph(const float* xb, int64_t nb, int32_t d, int32_
                        0, s, D1.as<float>(), I1.as<int64_t>(), nnodes, k, node0, D, I);
     MK_LAUNCHED();
     return MK_OK;
+}
+
+extern "C" mk_status mk_knn_search_host(const float* xq, int64_t nq, const float* xb_host,
+                                        int64_t nb, int32_t d, int32_t k, mk_metric metric,
+                                        int64_t chunk_rows, float* D, int64_t* I,
+                                        mk_stream_t stream) {
+    MK_REQUIRE(nq >= 0 && nb >= 0, MK_ERR_INVALID_ARG, "nq and nb must be >= 0");
+    MK_REQUIRE(d >= 1 && d <= 256, MK_ERR_UNSUPPORTED, "d must be in [1, 256]");
+    MK_REQUIRE(k >= 1, MK_ERR_INVALID_ARG, "k must be >= 1");
+    MK_REQUIRE(k <= mk::kMaxK, MK_ERR_UNSUPPORTED, "k must be <= 1024");
+    MK_REQUIRE(nb < 0xFFFFFFFFll, MK_ERR_UNSUPPORTED, "nb must be < 2^32 - 1");
+    MK_REQUIRE(chunk_rows >= 1 && chunk_rows < (1ll << 31), MK_ERR_INVALID_ARG,
+               "chunk_rows must be in [1, 2^31)");
+    MK_REQUIRE(metric == MK_METRIC_L2 || metric == MK_METRIC_IP, MK_ERR_INVALID_ARG, "bad metric");
+    if (nq == 0) return MK_OK;
+    MK_REQUIRE(xq && D && I && (xb_host || nb == 0), MK_ERR_INVALID_ARG, "null pointer");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool largest = metric == MK_METRIC_IP;
+    if (nb <= chunk_rows) {
+        // one chunk: copy and search in order on the caller's stream
+        mk::Scratch buf;
+        MK_TRY(buf.alloc(sizeof(float) * (size_t)(nb > 0 ? nb : 1) * d, s));
+        if (nb > 0)
+            MK_HIP(hipMemcpyAsync(buf.ptr, xb_host, sizeof(float) * (size_t)nb * d,
+                                  hipMemcpyHostToDevice, s));
+        MK_TRY(mk::knn_search(xq, nq, buf.as<float>(), nullptr, nb, d, k, metric, D, I, s));
+        MK_HIP(hipStreamSynchronize(s));
+        return MK_OK;
+    }
+    const int64_t nchunks = mk::ceil_div(nb, chunk_rows);
+    MK_REQUIRE(nchunks <= (1 << 20), MK_ERR_INVALID_ARG, "too many chunks");
+    mk::Scratch buf[2], Dc, Ic, keys;
+    for (auto& b : buf) MK_TRY(b.alloc(sizeof(float) * (size_t)chunk_rows * d, s));
+    MK_TRY(Dc.alloc(sizeof(float) * (size_t)nq * k, s));
+    MK_TRY(Ic.alloc(sizeof(int64_t) * (size_t)nq * k, s));
+    MK_TRY(keys.alloc(sizeof(uint64_t) * (size_t)nq * nchunks * k, s));
+    // copies run on a second stream, one chunk ahead of the searches: the
+    // copy of chunk c + 1 overlaps the search of chunk c; the copy into a
+    // buffer waits for the search that last read it
+    hipStream_t cs = nullptr;
+    MK_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipEvent_t ready[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr}, start = nullptr;
+    mk_status st = MK_OK;
+    auto fail = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && st == MK_OK) {
+            mk::set_error(std::string("mk_knn_search_host: ") + what + ": " + hipGetErrorString(e));
+            st = e == hipErrorOutOfMemory ? MK_ERR_OOM : MK_ERR_DEVICE;
+        }
+        return st != MK_OK;
+    };
+    for (int i = 0; i < 2 && st == MK_OK; ++i) {
+        fail(hipEventCreateWithFlags(&ready[i], hipEventDisableTiming), "event");
+        fail(hipEventCreateWithFlags(&freed[i], hipEventDisableTiming), "event");
+    }
+    if (st == MK_OK) fail(hipEventCreateWithFlags(&start, hipEventDisableTiming), "event");
+    // the staging buffers come from the caller's stream's allocator
+    if (st == MK_OK) fail(hipEventRecord(start, s), "record");
+    if (st == MK_OK) fail(hipStreamWaitEvent(cs, start, 0), "wait");
+    auto copy = [&](int64_t c) {
+        const int64_t r0 = c * chunk_rows;
+        const int64_t n = nb - r0 < chunk_rows ? nb - r0 : chunk_rows;
+        const int b = (int)(c & 1);
+        if (c >= 2 && fail(hipStreamWaitEvent(cs, freed[b], 0), "wait")) return;
+        if (fail(hipMemcpyAsync(buf[b].ptr, xb_host + r0 * d, sizeof(float) * (size_t)n * d,
+                                hipMemcpyHostToDevice, cs), "copy"))
+            return;
+        fail(hipEventRecord(ready[b], cs), "record");
+    };
+    if (st == MK_OK) copy(0);
+    for (int64_t c = 0; c < nchunks && st == MK_OK; ++c) {
+        if (c + 1 < nchunks) copy(c + 1);
+        if (st != MK_OK) break;
+        const int b = (int)(c & 1);
+        const int64_t r0 = c * chunk_rows;
+        const int64_t n = nb - r0 < chunk_rows ? nb - r0 : chunk_rows;
+        if (fail(hipStreamWaitEvent(s, ready[b], 0), "wait")) break;
+        st = mk::knn_search(xq, nq, buf[b].as<float>(), nullptr, n, d, k, metric, Dc.as<float>(),
+                            Ic.as<int64_t>(), s);
+        if (st != MK_OK) break;
+        hipLaunchKernelGGL(mk::chunk_keys_kernel,
+                           dim3((unsigned)std::min<int64_t>(mk::ceil_div(nq * k, 256), 1 << 20)),
+                           dim3(256), 0, s, Dc.as<float>(), Ic.as<int64_t>(), nq, k, (int32_t)c,
+                           (int32_t)nchunks, r0, (int32_t)largest, keys.as<uint64_t>());
+        if (fail(hipGetLastError(), "launch")) break;
+        fail(hipEventRecord(freed[b], s), "record");
+    }
+    if (st == MK_OK)
+        st = mk::merge_key_lists(keys.as<uint64_t>(), nq, (int32_t)nchunks, k, D, I, s, nullptr,
+                                 nullptr, largest);
+    // every copy has been waited on by a search (or the loop stopped): drain
+    // the copy stream before it and the events go away
+    (void)hipStreamSynchronize(cs);
+    (void)hipStreamSynchronize(s);
+    for (int i = 0; i < 2; ++i) {
+        if (ready[i]) (void)hipEventDestroy(ready[i]);
+        if (freed[i]) (void)hipEventDestroy(freed[i]);
+    }
+    if (start) (void)hipEventDestroy(start);
+    (void)hipStreamDestroy(cs);
+    return st;
 }
 
 extern "C" mk_status mk_debug_pool_drops(int64_t* count) {

@@ -27,7 +27,9 @@ mk_status knn_launch(const float* xq, int64_t nq, const float* xb, const float* 
     if (sizing_only(arena)) return MK_OK;
     MK_TRY(clear_bounds(KR, bound.as<uint32_t>(), nq, nchunks, stream));
     const int64_t nblocks = nqb * nchunks;
-    MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
+    // the grid's work-item count must fit 32 bits
+    MK_REQUIRE(nblocks * 64 * (kProducers + S::NC) < (1ll << 32), MK_ERR_UNSUPPORTED,
+               "problem too large for one launch (search fewer queries per call)");
     unsigned long long* drops = nullptr;
     MK_TRY(pool_drop_counter(&drops));
     FusedArgs a{xq, xb, yn, nullptr, nullptr, nq, nb, d, d, chunk_len, (int32_t)nchunks,

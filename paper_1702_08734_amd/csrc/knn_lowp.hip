@@ -78,12 +78,22 @@ mk_status quantize(const float* x, int64_t n, int32_t d, int32_t prec, void* out
                    hipStream_t s) {
     if (n == 0) return MK_OK;
     const int32_t ld = lowp_stride(d);
-    const dim3 grid((unsigned)ceil_div(n, 4)), block(256);
-    if (prec == 1)
-        hipLaunchKernelGGL(quantize_rows_kernel<1>, grid, block, 0, s, x, n, d, ld, out, inv);
-    else
-        hipLaunchKernelGGL(quantize_rows_kernel<2>, grid, block, 0, s, x, n, d, ld, out, inv);
-    MK_LAUNCHED();
+    const size_t esize = prec == 1 ? 2 : 1;
+    // launches of at most 2^24 rows (2^30 work-items: under the 32-bit
+    // work-item count of a grid dimension)
+    constexpr int64_t kRows = 1ll << 24;
+    for (int64_t r0 = 0; r0 < n; r0 += kRows) {
+        const int64_t m = n - r0 < kRows ? n - r0 : kRows;
+        const dim3 grid((unsigned)ceil_div(m, 4)), block(256);
+        const float* xr = x + r0 * d;
+        void* o = static_cast<unsigned char*>(out) + (size_t)r0 * ld * esize;
+        float* iv = inv ? inv + r0 : nullptr;
+        if (prec == 1)
+            hipLaunchKernelGGL(quantize_rows_kernel<1>, grid, block, 0, s, xr, m, d, ld, o, iv);
+        else
+            hipLaunchKernelGGL(quantize_rows_kernel<2>, grid, block, 0, s, xr, m, d, ld, o, iv);
+        MK_LAUNCHED();
+    }
     return MK_OK;
 }
 
@@ -102,7 +112,9 @@ mk_status lowp_launch(const float* xq, const void* xq_lp, const float* xq_inv, i
     MK_TRY(bound.alloc(sizeof(uint32_t) * (size_t)bound_words(KR, nq, nchunks), stream));
     MK_TRY(clear_bounds(KR, bound.as<uint32_t>(), nq, nchunks, stream));
     const int64_t nblocks = nqb * nchunks;
-    MK_REQUIRE(nblocks < (1ll << 31), MK_ERR_UNSUPPORTED, "problem too large for one launch");
+    // the grid's work-item count must fit 32 bits
+    MK_REQUIRE(nblocks * 64 * (kProducers + S::NC) < (1ll << 32), MK_ERR_UNSUPPORTED,
+               "problem too large for one launch (search fewer queries per call)");
     const int32_t ld = lowp_stride(d);
     unsigned long long* drops = nullptr;
     MK_TRY(pool_drop_counter(&drops));

@@ -213,9 +213,26 @@ mk_status kselect_dispatch(const float* a, int64_t nrows, int64_t len, int32_t k
 
 mk_status merge_key_lists(const uint64_t* partial, int64_t nrows, int32_t nseg, int32_t k,
                           float* vals, int64_t* idx, hipStream_t s, uint64_t* keys_out,
-                          const int64_t* seg_offs) {
+                          const int64_t* seg_offs, bool largest) {
     if (nrows == 0) return MK_OK;
     const dim3 grid((unsigned)ceil_div(nrows, kWavesPerBlock)), block(64 * kWavesPerBlock);
+    if (largest) {
+        MK_REQUIRE(!keys_out, MK_ERR_INVALID_ARG, "largest-first merges emit values");
+        switch (queue_regs(k)) {
+            case 1: hipLaunchKernelGGL((kselect_merge<1, SelParams<1>::T, true>), grid, block, 0,
+                                       s, partial, nrows, nseg, k, vals, idx, keys_out, seg_offs); break;
+            case 2: hipLaunchKernelGGL((kselect_merge<2, SelParams<2>::T, true>), grid, block, 0,
+                                       s, partial, nrows, nseg, k, vals, idx, keys_out, seg_offs); break;
+            case 4: hipLaunchKernelGGL((kselect_merge<4, SelParams<4>::T, true>), grid, block, 0,
+                                       s, partial, nrows, nseg, k, vals, idx, keys_out, seg_offs); break;
+            case 8: hipLaunchKernelGGL((kselect_merge<8, SelParams<8>::T, true>), grid, block, 0,
+                                       s, partial, nrows, nseg, k, vals, idx, keys_out, seg_offs); break;
+            default: hipLaunchKernelGGL((kselect_merge<16, SelParams<16>::T, true>), grid, block, 0,
+                                        s, partial, nrows, nseg, k, vals, idx, keys_out, seg_offs); break;
+        }
+        MK_LAUNCHED();
+        return MK_OK;
+    }
     switch (queue_regs(k)) {
         case 1: hipLaunchKernelGGL((kselect_merge<1, SelParams<1>::T, false>), grid, block, 0, s,
                                    partial, nrows, nseg, k, vals, idx, keys_out, seg_offs); break;

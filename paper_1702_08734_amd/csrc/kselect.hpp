@@ -35,10 +35,13 @@ template <> struct SelParams<16> { static constexpr int T = 8; };
 // become (+inf, -1) -- or, if keys_out is given, the sorted keys themselves
 // (keys_out[row][64 * queue_regs(k)], sentinel padded).  With seg_offs the
 // lists of row r are seg_offs[r] .. seg_offs[r + 1] - 1 (nseg unused).  The
-// second pass of the two-pass k-selection of Section 5.3.
+// second pass of the two-pass k-selection of Section 5.3.  largest: keys
+// hold negated scores (largest first) and the values are emitted negated
+// back, padding -inf.
 mk_status merge_key_lists(const uint64_t* partial, int64_t nrows, int32_t nseg, int32_t k,
                           float* vals, int64_t* idx, hipStream_t s,
-                          uint64_t* keys_out = nullptr, const int64_t* seg_offs = nullptr);
+                          uint64_t* keys_out = nullptr, const int64_t* seg_offs = nullptr,
+                          bool largest = false);
 
 // Exact k-NN (knn.hip); yn may be null (then computed) for L2.
 // With an arena every scratch buffer is carved from it (nothing is

@@ -9,9 +9,11 @@
 // W2 [h, h], b2 [h], w3 [h], b3 [1].
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "common.hpp"
+#include "fileio.hpp"
 #include "mlp.hpp"
 #include "profile.hpp"
 
@@ -558,5 +560,76 @@ extern "C" mk_status mk_mlp_train_epoch(mk_mlp* net, const float* F, int64_t n, 
         MK_TRY(mk::backward(net, y, perm + off, B, p, losses ? losses + b : nullptr, s));
         MK_TRY(mk::adam(net, lr, s));
     }
+    return MK_OK;
+}
+
+// ---------------------------------------------------------------- save / load
+namespace {
+constexpr char kNetMagic[8] = {'M', 'K', 'M', 'L', 'P', '\0', '\0', '\0'};
+constexpr uint32_t kNetVersion = 1;
+}  // namespace
+
+extern "C" mk_status mk_mlp_shape(const mk_mlp* net, int32_t* din, int32_t* hidden,
+                                  int32_t* prec) {
+    MK_REQUIRE(net, MK_ERR_INVALID_ARG, "null network");
+    if (din) *din = net->din;
+    if (hidden) *hidden = net->h;
+    if (prec) *prec = (int32_t)net->prec;
+    return MK_OK;
+}
+
+extern "C" mk_status mk_mlp_save(const mk_mlp* net, const char* path) {
+    MK_REQUIRE(net && path, MK_ERR_INVALID_ARG, "null pointer");
+    MK_HIP(hipDeviceSynchronize());
+    mk::BinFile f(path, "wb");
+    MK_REQUIRE(f.ok(), MK_ERR_INVALID_ARG, std::string("cannot open ") + path + " for writing");
+    const int32_t prec = (int32_t)net->prec;
+    const bool head = f.put(kNetMagic, 8) && f.put_v(kNetVersion) && f.put_v(net->din) &&
+                      f.put_v(net->h) && f.put_v(prec) && f.put_v(net->step);
+    MK_REQUIRE(head, MK_ERR_INVALID_ARG, std::string("write to ") + path + " failed");
+    const size_t pb = sizeof(float) * (size_t)net->np;
+    MK_TRY(mk::put_device(f, net->theta, pb));
+    MK_TRY(mk::put_device(f, net->m1, pb));
+    MK_TRY(mk::put_device(f, net->m2, pb));
+    MK_TRY(mk::put_device(f, net->mean, sizeof(float) * (size_t)net->din));
+    MK_TRY(mk::put_device(f, net->inv_std, sizeof(float) * (size_t)net->din));
+    MK_REQUIRE(f.close(), MK_ERR_INVALID_ARG, std::string("write to ") + path + " failed");
+    return MK_OK;
+}
+
+extern "C" mk_status mk_mlp_load(const char* path, mk_mlp** out) {
+    MK_REQUIRE(path && out, MK_ERR_INVALID_ARG, "null pointer");
+    *out = nullptr;
+    mk::BinFile f(path, "rb");
+    MK_REQUIRE(f.ok(), MK_ERR_INVALID_ARG, std::string("cannot open ") + path);
+    char magic[8];
+    uint32_t version = 0;
+    int32_t din = 0, h = 0, prec = 0;
+    int64_t step = 0;
+    const bool head = f.get(magic, 8) && f.get_v(version) && f.get_v(din) && f.get_v(h) &&
+                      f.get_v(prec) && f.get_v(step);
+    MK_REQUIRE(head && std::memcmp(magic, kNetMagic, 8) == 0, MK_ERR_INVALID_ARG,
+               std::string(path) + " is not a network file");
+    MK_REQUIRE(version == kNetVersion, MK_ERR_UNSUPPORTED,
+               std::string(path) + ": unknown network file version");
+    MK_REQUIRE(step >= 0, MK_ERR_INVALID_ARG, std::string(path) + ": bad step count");
+    mk_mlp* net = nullptr;
+    MK_TRY(mk_mlp_create(din, h, (mk_precision)prec, &net));
+    const size_t pb = sizeof(float) * (size_t)net->np;
+    mk_status st = mk::get_device(f, net->theta, pb);
+    if (st == MK_OK) st = mk::get_device(f, net->m1, pb);
+    if (st == MK_OK) st = mk::get_device(f, net->m2, pb);
+    if (st == MK_OK) st = mk::get_device(f, net->mean, sizeof(float) * (size_t)din);
+    if (st == MK_OK) st = mk::get_device(f, net->inv_std, sizeof(float) * (size_t)din);
+    if (st == MK_OK && !f.at_end()) {
+        mk::set_error(std::string(path) + " has trailing bytes");
+        st = MK_ERR_INVALID_ARG;
+    }
+    if (st != MK_OK) {
+        mk_mlp_destroy(net);
+        return st;
+    }
+    net->step = step;
+    *out = net;
     return MK_OK;
 }

@@ -70,14 +70,20 @@ def uniform_rows(nrows: int, length: int, seed: int) -> np.ndarray:
 
 
 class Mixture:
-    """Gaussian mixture with uniform weights, centres N(0, 4I), scales U[0.5, 1.5]."""
+    """Gaussian mixture with uniform weights, centres N(0, 4I), scales U[0.5, 1.5]
+    (or, with log_scales=(lo, hi), scales log-uniform in [lo, hi]: components
+    of very different densities)."""
 
-    def __init__(self, ncomp: int, d: int, seed: int):
+    def __init__(self, ncomp: int, d: int, seed: int, log_scales=None):
         rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
         self.ncomp = ncomp
         self.d = d
         self.mu = 2.0 * rng.standard_normal((ncomp, d))
-        self.sigma = rng.uniform(0.5, 1.5, size=ncomp)
+        if log_scales is None:
+            self.sigma = rng.uniform(0.5, 1.5, size=ncomp)
+        else:
+            lo, hi = log_scales
+            self.sigma = np.exp(rng.uniform(np.log(lo), np.log(hi), size=ncomp))
 
     def sample(self, n: int, seed: int, unit_norm: bool = False) -> np.ndarray:
         mu, sigma, ncomp = self.mu, self.sigma, self.ncomp
@@ -142,7 +148,8 @@ def ivfpq_workload(nb: int = 10_000_000, nq: int = 10_000, nt: int = 500_000):
             "nprobes": (1, 8, 16, 32, 64, 128), "rerank": (256, 1024),
             "learn_rerank": 256, "learn_cap": 32, "learn_fixed_nprobes": tuple(range(1, 13)),
             "learn_train": 200_000, "learn_epochs": 30, "serve_requests": 2000,
-            "serve_load": (0.5, 0.8), "base": 103, "mix": (1000, 128, (103, 99))}
+            "serve_load": (0.5, 0.8), "base": 103, "mix": (1000, 128, (103, 99)),
+            "graph_settings": ((4, 0), (16, 0), (4, 64), (8, 128), (16, 256))}
 
 
 def ivfpq_large_workload(nb: int = 50_000_000, nq: int = 10_000, nt: int = 500_000):
@@ -155,7 +162,7 @@ def ivfpq_large_workload(nb: int = 50_000_000, nq: int = 10_000, nt: int = 500_0
     return {"xb": xb, "xq": xq, "sample": sample, "nlist": 16384, "M": 16,
             "coarse_init": choose_rows(nt, 16384, (105, 3)),
             "pq_init": pq_init_rows(nt, 16, (105, 4)), "k": 10,
-            "learn_rerank": 256, "learn_cap": 64, "learn_fixed_nprobes": tuple(range(1, 17)),
+            "learn_rerank": 1024, "learn_cap": 64, "learn_fixed_nprobes": tuple(range(1, 25)),
             "learn_train": 200_000, "learn_epochs": 30, "serve_requests": 2000,
             "serve_load": (0.5, 0.8), "base": 105, "mix": (1000, 128, (105, 99))}
 

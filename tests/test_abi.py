@@ -54,3 +54,20 @@ def test_argument_errors_need_no_device(libhandle):
     libhandle.mk_last_error.restype = ctypes.c_char_p
     libhandle.mk_knn_search(None, 1, None, 1, 0, 5, 0, None, None, None)
     assert b"d must be" in libhandle.mk_last_error()
+
+
+def test_bad_files_refused_without_a_device(libhandle, tmp_path):
+    # the header is checked before any HIP call
+    import ctypes as C
+    vp = C.c_void_p
+    for fn in ("mk_ivfpq_load", "mk_mlp_load"):
+        f = getattr(libhandle, fn)
+        f.restype = C.c_int32
+        f.argtypes = [C.c_char_p, C.POINTER(vp)]
+        out = vp(1)
+        missing = str(tmp_path / "none.bin").encode()
+        assert f(missing, C.byref(out)) == -1 and not out.value
+        junk = tmp_path / "junk.bin"
+        junk.write_bytes(b"not an index or network file at all")
+        out = vp(1)
+        assert f(str(junk).encode(), C.byref(out)) == -1 and not out.value

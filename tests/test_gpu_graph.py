@@ -222,7 +222,56 @@ def test_ivfpq_graph_duplicate_nodes(api, graph_index):
     assert np.mean(I[:, 0] == np.arange(200)) > 0.9
 
 
+@pytest.mark.parametrize("k,nprobe,R", [(10, 4, 64), (20, 16, 256)])
+def test_ivfpq_graph_rerank_matches_oracle(api, graph_index, k, nprobe, R):
+    # ADC short list of R entries (the node excluded), re-ranked exactly
+    ix, xb, coarse, books, offs, codes, ids = graph_index
+    say(f"ivfpq graph re-rank k={k} nprobe={nprobe} R={R}")
+    D, I = ix.knn_graph(dev(xb), k, nprobe, R=R)
+    torch.cuda.synchronize()
+    D, I = D.cpu().numpy(), I.cpu().numpy()
+    assert not np.any(I == np.arange(len(xb))[:, None]), "a node is its own neighbour"
+    rows = np.concatenate([np.arange(0, 50_000, 1013), np.arange(40_000, 40_010)])
+    Da, Ia = oracle.ivfpq_search(xb[rows], coarse, books, offs, codes, ids, R + 1, nprobe,
+                                 exclude=rows)
+    Do, Io = oracle.ivfpq_search_rerank(xb[rows], coarse, books, offs, codes, ids, xb, k, nprobe,
+                                        R, exclude=rows)
+    skipped, fails = 0, []
+    for j, q in enumerate(rows):
+        x = xb[q].astype(np.float64)
+        cd = np.sort(((coarse.astype(np.float64) - x) ** 2).sum(1))
+        probe_amb = nprobe < len(coarse) and cd[nprobe] - cd[nprobe - 1] <= RTOL * cd[nprobe]
+        a = Da[j]
+        list_amb = Ia[j, R] >= 0 and a[R] - a[R - 1] <= RTOL * a[R]
+        if probe_amb or list_amb:
+            skipped += 1
+            continue
+        gi, gd = I[q][I[q] >= 0], D[q][I[q] >= 0].astype(np.float64)
+        nexp = int((Io[j] >= 0).sum())
+        if len(gi) != nexp:
+            fails.append(f"node {q}: {len(gi)} results, expected {nexp}")
+            continue
+        delta = ((xb[gi].astype(np.float64) - x) ** 2).sum(1)
+        floor = 1e-3 * ((x ** 2).sum() + (xb[gi].astype(np.float64) ** 2).sum(1))
+        if np.any(np.abs(gd - delta) > RTOL * np.maximum(delta, floor)):
+            fails.append(f"node {q}: distance off")
+        od, oi = Do[j][:nexp], Io[j][:nexp]
+        band = set(oi[np.abs(od - od[-1]) <= RTOL * max(od[-1], 1e-30)].tolist())
+        if not (set(oi.tolist()) - band) <= set(gi.tolist()):
+            fails.append(f"node {q}: sets differ beyond the band")
+        for r in range(nexp):
+            lo = r == 0 or od[r] - od[r - 1] > RTOL * od[r]
+            hi = r + 1 >= nexp or od[r + 1] - od[r] > RTOL * od[r]
+            if lo and hi and gi[r] != oi[r]:
+                fails.append(f"node {q}: rank {r} id {gi[r]} != oracle {oi[r]}")
+                break
+    assert not fails, fails[:10]
+    assert skipped <= len(rows) // 10
+
+
 def test_ivfpq_graph_errors(api, graph_index):
     ix, xb, *_ = graph_index
     with pytest.raises(api.MKError):
         ix.knn_graph(dev(xb), 10, 4, node0=49_990, nnodes=20)
+    with pytest.raises(api.MKError):
+        ix.knn_graph(dev(xb), 10, 4, R=5)  # R < k

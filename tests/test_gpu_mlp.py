@@ -276,3 +276,72 @@ def test_learned_search_matches_oracle(api, index):
                                offs, codes, ids, k, int(tau[j]))
         bad += len(fails)
     assert bad == 0
+
+
+# ------------------------------------------------------------ what the network gains
+@pytest.fixture(scope="module")
+def gain_setup(api):
+    # 200,000 rows of a 50-component mixture in d = 64 whose component scales
+    # are log-uniform in [0.2, 3] (dense and sparse regions), 2,048 lists: how
+    # many lists a query needs then depends on where it falls, which the
+    # coarse distances reveal.  (With the equal-scale mixture of the
+    # benchmark workloads the needed count is close to unpredictable from
+    # the features, and the network cannot gain.)  Training queries are
+    # labelled by the exact nearest neighbour from the exact search (itself
+    # oracle-checked).
+    say("gain test: build index, labels, train")
+    mix = synth.Mixture(50, 64, (33, 0), log_scales=(0.2, 3.0))
+    xb = mix.sample(200_000, (33, 1))
+    xt = xb[synth.choose_rows(len(xb), 100_000, (33, 2))]
+    nlist, M, cap = 2048, 16, 64
+    ix = api.IVFPQ(64, nlist, M)
+    ix.train(dev(xt), 10, synth.choose_rows(len(xt), nlist, (33, 3)),
+             synth.pq_init_rows(len(xt), M, (33, 4)))
+    xbd = dev(xb)
+    ix.add(xbd)
+    xtr = dev(mix.sample(100_000, (33, 5)))
+    nn = api.knn_search(xtr, xbd, 1)[1][:, 0].contiguous()
+    F = ix.probe_features(xtr)
+    target, label = ix.probe_labels(xtr, nn, cap)
+    net = api.MLP(64 + 32, H, "bf16")
+    net.set_params(synth.mlp_init(64 + 32, H, (33, 6)))
+    net.fit_standardization(F)
+    for ep in range(20):
+        net.train_epoch(F, target, dev(synth.permutation(F.shape[0], (33, 7, ep))), 1024, 1e-3)
+    xev = dev(mix.sample(4_000, (33, 8)))
+    gev = api.knn_search(xev, xbd, 1)[1][:, 0].cpu().numpy()
+    return {"ix": ix, "xb": xbd, "net": net, "xev": xev, "gev": gev, "cap": cap,
+            "label_mean": float(label.float().mean().item())}
+
+
+def test_learned_probe_count_gain(api, gain_setup):
+    # At equal recall (true nearest neighbour among the 10 returned, after the
+    # same exact re-rank of 128 ADC candidates), the trained network must probe
+    # fewer lists on average than the smallest fixed probe count reaching that
+    # recall on the same queries.  The offset delta is the smallest on a 0.05
+    # grid reaching the fixed count's recall.
+    g = gain_setup
+    ix, xb, net, xev, gev, cap = g["ix"], g["xb"], g["net"], g["xev"], g["gev"], g["cap"]
+    R, k = 128, 10
+
+    def recall(I):
+        I = I.cpu().numpy()
+        return float(np.mean([gev[j] in I[j] for j in range(len(gev))]))
+
+    fixed = {t: recall(ix.search_rerank(xev, k, t, R, xb)[1]) for t in range(1, 33)}
+    target = 0.9
+    tau_f = min((t for t, r in fixed.items() if r >= target), default=None)
+    assert tau_f is not None, f"no fixed probe count reaches {target}: {fixed}"
+    target = fixed[tau_f]  # the recall the fixed count actually reaches
+    learned = None
+    for delta in np.arange(-1.0, 4.0001, 0.05):
+        _, I, tau = ix.search_learned(net, float(delta), xev, k, cap, R, xb)
+        r = recall(I)
+        if r >= target:
+            learned = (float(delta), r, float(tau.float().mean().item()))
+            break
+    say(f"gain: label mean {g['label_mean']:.2f}; fixed tau {tau_f} recall {target:.4f}; "
+        f"learned (delta, recall, mean tau) = {learned}; fixed curve {fixed}")
+    assert learned is not None, "the learned count never reaches the fixed count's recall"
+    assert learned[2] < tau_f, (
+        f"learned mean probes {learned[2]:.2f} not below the fixed {tau_f} at recall {target:.4f}")
