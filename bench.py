@@ -37,7 +37,8 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0
 FP8_MFMA_PEAK_TFLOPS = 5000.0
 KS = (1, 32, 256, 1024)
 PMC_FILE = os.path.join(ROOT, "profiles", "knn_fused_exact_large_pmc.json")
-KERNEL_SOURCES = ["knn.hip", "fused.hpp", "wave_select.hpp", "kselect.hpp"]
+# sources of the fused kernel and its launch configuration
+KERNEL_SOURCES = ["fused.hpp", "wave_select.hpp", "kselect.hpp", "knn_impl.hpp", "common.hpp"]
 
 
 def kernel_source_hash() -> str:
@@ -581,13 +582,23 @@ def ivf_large_run(api, synth, torch):
 def ivf_large_scan_profile(api, synth, torch):
     """Only the ADC list scans of the 50,000,000-vector index at nprobe 16
     and 64 (for hardware-counter runs restricted to the scan kernel)."""
-    _, ix, xb, xq, _, _ = build_large_index(api, synth, torch)
+    import numpy as np
+    w, ix, xb, xq, _, _ = build_large_index(api, synth, torch)
+    offs, _, _ = ix.get_lists()
+    sizes = np.diff(offs)
+    _, probe = api.knn_search(xq, torch.from_numpy(ix.get_quantizers()[0]).cuda(), 64)
+    probe = probe.cpu().numpy()
+    out = {"profiled": "ivf_scan at nprobe 16 and 64, 3 searches each, 10,000 queries, k = 100",
+           "algorithmic_bytes_per_search": {}}
     for nprobe in (16, 64):
         progress(f"ivf-large scan profile: nprobe {nprobe}")
         for _ in range(3):
             ix.search(xq, 100, nprobe)
         torch.cuda.synchronize()
-    return {"profiled": "ivf_scan at nprobe 16 and 64, 3 searches each, 10,000 queries, k = 100"}
+        scanned = int(sizes[probe[:, :nprobe]].sum())
+        out["algorithmic_bytes_per_search"][str(nprobe)] = {
+            "scanned_entries": scanned, "bytes": scanned * (w["M"] + 4)}
+    return out
 
 
 def main() -> int:
@@ -607,6 +618,9 @@ def main() -> int:
                     help="only the list scans of the 50,000,000-vector index (profiling)")
     ap.add_argument("--skip-large", action="store_true",
                     help="leave out the 50,000,000-vector IVFADC section")
+    ap.add_argument("--section", default=None,
+                    help="only this extra section (small_exact, kselect, ivfpq, lowp, ivf_large), "
+                         "for profiling runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are "
@@ -629,6 +643,11 @@ def main() -> int:
         return 0
     if args.ivf_large_scan:
         print(json.dumps(ivf_large_scan_profile(api, synth, torch)), flush=True)
+        return 0
+    if args.section:
+        fns = {"small_exact": small_exact_section, "kselect": kselect_section,
+               "ivfpq": ivfpq_section, "lowp": lowp_section, "ivf_large": ivf_large_run}
+        print(json.dumps({args.section: fns[args.section](api, synth, torch)}), flush=True)
         return 0
 
     progress("exact: generating 1,000,000 x 128 mixture")

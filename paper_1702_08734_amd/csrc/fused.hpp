@@ -150,10 +150,19 @@ struct MultiSelect {
     // false means no candidate.  A query whose scores all lose to its current
     // threshold is skipped after one compare per lane.
     __device__ __forceinline__ void offer(const float (&score)[QW], uint32_t idx, bool ok) {
+        // one compare per query into a wave mask, one test of their union:
+        // the common case (no query takes anything) costs no per-query branch
+        uint64_t cand[QW], any = 0;
+#pragma unroll
+        for (int q = 0; q < QW; ++q) {
+            cand[q] = __ballot(ok && score[q] <= kf[q]);
+            any |= cand[q];
+        }
+        if (!any) return;
         uint32_t full = 0;
 #pragma unroll
         for (int q = 0; q < QW; ++q) {
-            if (__any(ok && score[q] <= kf[q])) {
+            if (cand[q]) {
                 const uint64_t key = ok ? make_key(score[q], idx) : kSentinel;
                 const uint64_t kth = ((uint64_t)kh[q] << 32) | kl[q];
                 const bool take = key < kth;
@@ -248,6 +257,9 @@ struct PoolSelect {
     vqf kf;              // its score
     vq bdu;              // order-mapped score bound from the chunks' rank points
     int cnt[QW];         // keys in each query's pool
+    // set when an append takes some pool past the refine level / the
+    // urgency level, so that the per-step checks cost one scalar test
+    bool need_cut, is_urgent;
     uint64_t* wbase;     // pool of query q at wbase + q * wstride
     int64_t wstride;
     uint32_t* rpub;      // rank points of query q, this chunk, at rpub + q * rstride
@@ -276,6 +288,7 @@ struct PoolSelect {
         kl = kh = ~0u;
         kf = INFINITY;
         bdu = kNoBound;
+        need_cut = is_urgent = false;
 #pragma unroll
         for (int q = 0; q < QW; ++q) {
             cnt[q] = 0;
@@ -446,9 +459,17 @@ struct PoolSelect {
     __device__ __forceinline__ void offer(const float (&score)[QW], uint32_t idx, bool ok) {
         uint32_t full = 0;
         const int lane = lane_id();
+        // one compare per query into a wave mask, one test of their union
+        uint64_t cand[QW], any = 0;
 #pragma unroll
         for (int q = 0; q < QW; ++q) {
-            if (__any(ok && score[q] <= kf[q])) {
+            cand[q] = __ballot(ok && score[q] <= kf[q]);
+            any |= cand[q];
+        }
+        if (!any) return;
+#pragma unroll
+        for (int q = 0; q < QW; ++q) {
+            if (cand[q]) {
                 const uint64_t key = ok ? make_key(score[q], idx) : kSentinel;
                 const uint64_t kth = ((uint64_t)kh[q] << 32) | kl[q];
                 const bool take = key < kth;
@@ -463,6 +484,8 @@ struct PoolSelect {
                             atomicAdd(drops, 1ull);
                     }
                     cnt[q] += __popcll(bal);
+                    need_cut |= cnt[q] > CAP - 64;
+                    is_urgent |= kBatch && cnt[q] > kUrgent;
                 }
             }
         }
@@ -478,14 +501,9 @@ struct PoolSelect {
     // overflow in the next offer is cut anyway.
     static constexpr bool kBatch = CAP >= 2048;
     static constexpr int kUrgent = CAP - 192;
-    __device__ __forceinline__ bool urgent() const {
-        if (!kBatch) return false;
-        bool u = false;
-#pragma unroll
-        for (int q = 0; q < QW; ++q) u |= cnt[q] > kUrgent;
-        return u;
-    }
+    __device__ __forceinline__ bool urgent() const { return kBatch && is_urgent; }
     __device__ __forceinline__ void refine_pools(bool batch) {
+        if (!batch && !need_cut) return;  // no pool can overflow in the next offer
         const int level = batch ? (keff + CAP) / 2 : CAP - 64;
         uint32_t m = 0;
 #pragma unroll
@@ -495,6 +513,12 @@ struct PoolSelect {
             m &= m - 1;
             refine(q, keff + 128);
         }
+        // every pool above `level` was cut to at most keff + 128 keys
+        need_cut = false;
+        bool u = false;
+#pragma unroll
+        for (int q = 0; q < QW; ++q) u |= cnt[q] > kUrgent;
+        is_urgent = kBatch && u;
     }
 
     // Cut every valid query's pool to at most 64*KR keys and pad it with
@@ -1017,9 +1041,12 @@ knn_fused(FusedArgs args) {
             if (L2) ynext = args.yn[c0 + lane];
             if (Op::SCALED) ysnext = args.yinv[c0 + lane];
         }
+        // bound exchanges: often early, while the queues fill (steps 0, 4, 8,
+        // 16, 32), then every 64 steps
+        int64_t next_x = args.bound ? 0 : nsteps + 1;
         for (int64_t s = 0; s <= nsteps; ++s) {
-            // often early, while the queues fill, then every 64 steps
-            if (args.bound && (s == 4 || s == 8 || s == 16 || s == 32 || (s & 63) == 0)) {
+            if (s == next_x) {
+                next_x = s == 0 ? 4 : s < 64 ? 2 * s : s + 64;
                 if constexpr (S::mem_queues)
                     exchange_ranks_wide(sel, args.bound, args.nchunks, qf, args.nq);
                 else
@@ -1029,9 +1056,11 @@ knn_fused(FusedArgs args) {
                 if constexpr (S::mem_queues) {
                     // consumers' urgency flags of the previous step
                     bool batch = false;
-                    if (s >= 2) {
+                    if constexpr (Sel::kBatch) {
+                        if (s >= 2) {
 #pragma unroll
-                        for (int c = 0; c < S::NC; ++c) batch |= urgent_flags[s & 1][c] != 0u;
+                            for (int c = 0; c < S::NC; ++c) batch |= urgent_flags[s & 1][c] != 0u;
+                        }
                     }
                     sel.refine_pools(batch);
                 }
@@ -1068,8 +1097,10 @@ knn_fused(FusedArgs args) {
                 }
                 sel.offer(score, (uint32_t)g, ok);
                 if constexpr (S::mem_queues) {
-                    const bool u = sel.urgent();
-                    if (lane == 0) urgent_flags[(s + 1) & 1][cw] = u ? 1u : 0u;
+                    if constexpr (Sel::kBatch) {
+                        const bool u = sel.urgent();
+                        if (lane == 0) urgent_flags[(s + 1) & 1][cw] = u ? 1u : 0u;
+                    }
                 }
             }
             __syncthreads();

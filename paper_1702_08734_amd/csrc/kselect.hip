@@ -8,6 +8,7 @@
 // its final result directly; otherwise the wave writes its k best keys and
 // pass 2 (one wave per row) selects over the segments' keys.
 #include "common.hpp"
+#include "fused.hpp"
 #include "kselect.hpp"
 #include "profile.hpp"
 #include "wave_select.hpp"
@@ -128,6 +129,96 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_pass1(
     }
 }
 
+// Pass 1 for queues of 256+ entries: a sorted queue is the wrong structure
+// there (every merge runs a network over the whole queue for a buffer of
+// new keys), so candidates that beat the current threshold are appended to
+// an unsorted pool of 2 * 64 * KR keys in device memory, cut back by a
+// radix selection inside the wave whenever it nears capacity (PoolSelect,
+// the fused search's selector).  At the end the pool is cut to 64 * KR keys,
+// which one WaveSelect pass sorts.
+template <int KR, bool LARGEST>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_pool(
+    const float* __restrict__ a, int64_t nrows, int64_t len, int32_t k, int32_t nseg,
+    int64_t seg_len, float* __restrict__ vals, int64_t* __restrict__ idx,
+    uint64_t* __restrict__ partial, uint64_t* __restrict__ pools,
+    unsigned long long* drops) {
+    constexpr int U = 4;
+    constexpr int NB = 512;
+    constexpr int T = SelParams<KR>::T;
+    using Pool = PoolSelect<KR, 1, NB>;
+    __shared__ float stage[kWavesPerBlock][4 * U][64];
+    __shared__ uint32_t bins[kWavesPerBlock][NB];
+    const int wave = threadIdx.x / 64;
+    const int lane = lane_id();
+    const int64_t unit = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    if (unit >= nrows * (int64_t)nseg) return;  // wave-uniform
+    const int64_t row = unit / nseg;
+    const int64_t seg = unit % nseg;
+    const int64_t lo = seg * seg_len;
+    const int64_t hi = lo + seg_len < len ? lo + seg_len : len;
+    const float* rp = a + row * len;
+    uint64_t* pool_keys = pools + unit * Pool::CAP;
+
+    Pool pool;
+    pool.init(k, pool_keys, 0, 1, nullptr, 1, bins[wave], drops);
+    auto offer = [&](float v, uint32_t i, bool ok) {
+        pool.refine_pools(false);  // room for the up to 64 keys one offer appends
+        const float sc[1] = {LARGEST ? -v : v};
+        pool.offer(sc, i, ok);
+    };
+    const bool aligned = (reinterpret_cast<uintptr_t>(rp + lo) & 15) == 0;
+    const int64_t vec_end = aligned ? lo + ((hi - lo) / (256 * U)) * (256 * U) : lo;
+    for (int64_t e = lo; e < vec_end; e += 256 * U) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            v[u] = *reinterpret_cast<const float4*>(rp + e + u * 256 + lane * 4);
+        const float th = pool.kf[0];
+        bool cand = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            cand |= (LARGEST ? -v[u].x : v[u].x) <= th;
+            cand |= (LARGEST ? -v[u].y : v[u].y) <= th;
+            cand |= (LARGEST ? -v[u].z : v[u].z) <= th;
+            cand |= (LARGEST ? -v[u].w : v[u].w) <= th;
+        }
+        if (__any(cand)) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                stage[wave][4 * u + 0][lane] = v[u].x;
+                stage[wave][4 * u + 1][lane] = v[u].y;
+                stage[wave][4 * u + 2][lane] = v[u].z;
+                stage[wave][4 * u + 3][lane] = v[u].w;
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+            for (int j = 0; j < 4 * U; ++j)
+                offer(stage[wave][j][lane], (uint32_t)(e + (j >> 2) * 256 + lane * 4 + (j & 3)),
+                      true);
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+#pragma unroll 1
+    for (int64_t e = vec_end; e < hi; e += 64) {
+        const int64_t i = e + lane;
+        offer(i < hi ? rp[i] : 0.f, (uint32_t)i, i < hi);
+    }
+    pool.finish();  // at most 64 KR keys left, sentinel padded to that length
+    // the pool's appends by every lane are visible to this wave's loads
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    WaveSelect<KR, T> ws;
+    ws.init(k);
+#pragma unroll 1
+    for (int r = 0; r < KR; ++r)
+        if (ws.push(pool_keys[r * 64 + lane])) ws.merge();
+    ws.finish();
+    if (nseg == 1) {
+        emit_values<KR, LARGEST>(ws.w, k, vals + row * k, idx + row * k);
+    } else {
+        emit_keys<KR>(ws.w, k, partial + unit * k);
+    }
+}
+
 // Pass 2: per row, select the k best of nseg * k partial keys (or, with
 // seg_offs, of the lists seg_offs[row] .. seg_offs[row + 1] - 1), written as
 // (value, index) pairs or, with keys_out, as the 64*KR-entry sorted key list.
@@ -173,18 +264,33 @@ mk_status kselect_launch(const float* a, int64_t nrows, int64_t len, int32_t k, 
     nseg = len > 0 ? ceil_div(len, seg_len) : 1;
     if (seg_len == 0) seg_len = 256;
 
-    Scratch part;
+    Scratch part, pools;
     if (nseg > 1) {
         mk_status st = part.alloc(sizeof(uint64_t) * (size_t)nrows * (size_t)nseg * (size_t)k, stream);
         if (st != MK_OK) return st;
     }
     const int64_t units = nrows * nseg;
+    // queues of 256+ entries over segments of at least 16 queue lengths:
+    // there most values are rejected and the pool's cuts are rare; short
+    // segments (every value a candidate) sort faster in the register queue
+    const bool pool = KR >= 4 && seg_len >= 16 * (int64_t)KS;
     {
         ProfScope prof("kselect_pass1", stream);
-        hipLaunchKernelGGL((kselect_pass1<KR, T, LARGEST>),
-                           dim3((unsigned)ceil_div(units, kWavesPerBlock)),
-                           dim3(64 * kWavesPerBlock), 0, stream, a, nrows, len, k, (int32_t)nseg,
-                           seg_len, vals, idx, part.as<uint64_t>());
+        if (pool) {
+            MK_TRY(pools.alloc(sizeof(uint64_t) * (size_t)units * 2 * KS, stream));
+            unsigned long long* drops = nullptr;
+            MK_TRY(pool_drop_counter(&drops));
+            hipLaunchKernelGGL((kselect_pool<KR, LARGEST>),
+                               dim3((unsigned)ceil_div(units, kWavesPerBlock)),
+                               dim3(64 * kWavesPerBlock), 0, stream, a, nrows, len, k,
+                               (int32_t)nseg, seg_len, vals, idx, part.as<uint64_t>(),
+                               pools.as<uint64_t>(), drops);
+        } else {
+            hipLaunchKernelGGL((kselect_pass1<KR, T, LARGEST>),
+                               dim3((unsigned)ceil_div(units, kWavesPerBlock)),
+                               dim3(64 * kWavesPerBlock), 0, stream, a, nrows, len, k,
+                               (int32_t)nseg, seg_len, vals, idx, part.as<uint64_t>());
+        }
         MK_LAUNCHED();
     }
     if (nseg > 1) {

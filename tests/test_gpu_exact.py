@@ -60,13 +60,17 @@ def test_kselect_segmented_rows(api, k):
     np.testing.assert_array_equal(v.cpu().numpy().astype(np.float64), vo)
 
 
-def test_kselect_unaligned_rows(api):
-    say("kselect unaligned")
+@pytest.mark.parametrize("k", [77, 300, 1000])
+def test_kselect_unaligned_rows(api, k):
+    # rows of 10,001 values: every row but the first starts off the 16-byte
+    # grid, so the element-wise path runs (k >= 129: candidate pools)
+    say(f"kselect unaligned k={k}")
     a = synth.uniform_rows(50, 10_001, (8, 0))
-    v, i = api.kselect(dev(a), 77)
+    v, i = api.kselect(dev(a), k)
     torch.cuda.synchronize()
-    vo, io = oracle.kselect(a, 77)
+    vo, io = oracle.kselect(a, k)
     np.testing.assert_array_equal(i.cpu().numpy(), io)
+    np.testing.assert_array_equal(v.cpu().numpy().astype(np.float64), vo)
 
 
 @pytest.mark.parametrize("k", [100, 1000])
