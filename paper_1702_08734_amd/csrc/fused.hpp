@@ -852,17 +852,36 @@ knn_fused(FusedArgs args) {
     constexpr int SK0 = 4 / (QPB * DPB) > 1 ? 4 / (QPB * DPB) : 1;
     constexpr int SK = SK0 < S4 ? SK0 : S4;
 
-    // Three database tiles in flight (loads run two steps ahead) when LDS
-    // allows, else two.
-    constexpr int NBUF = (3 * BN * GR * 16 + 2 * BN * LDQ * 4 <= 144 * 1024) ? 3 : 2;
     constexpr int LPW = NI / kProducers;  // tile loads per producer wave
     static_assert(NI % kProducers == 0, "tile loads split evenly over the producers");
+    // Database tiles in flight: as many buffers as the LDS left after the
+    // score slots and the smallest histograms holds (at most 6), loads
+    // running NBUF - 1 steps ahead; the steps' barriers do not wait for
+    // them, only each step's own tile is waited for (vmcnt counts up to 63
+    // outstanding loads).
+    constexpr int kLdsBytes = 160 * 1024;
+    constexpr int TILE_BYTES = BN * GR * 16;
+    constexpr int OTHER = 2 * BN * LDQ * 4 + (S::mem_queues ? S::NC * 128 * 4 : 0) + 512;
+    constexpr int NB_LDS = (kLdsBytes - OTHER) / TILE_BYTES;
+    constexpr int NB_VM = 63 / LPW + 1;
+    constexpr int NB0 = NB_LDS < NB_VM ? NB_LDS : NB_VM;
+    constexpr int NBUF = NB0 > 6 ? 6 : NB0 < 2 ? 2 : NB0;
+    constexpr int AHEAD = NBUF - 1;
 
-    __shared__ __align__(16) uint4 btile[NBUF][BN * GR];
+    // one statically named array per buffer, so that loads into one buffer
+    // and reads of another are told apart without waiting
+    __shared__ __align__(16) uint4 bt0[BN * GR];
+    __shared__ __align__(16) uint4 bt1[BN * GR];
+    __shared__ __align__(16) uint4 bt2[NBUF > 2 ? BN * GR : 1];
+    __shared__ __align__(16) uint4 bt3[NBUF > 3 ? BN * GR : 1];
+    __shared__ __align__(16) uint4 bt4[NBUF > 4 ? BN * GR : 1];
+    __shared__ __align__(16) uint4 bt5[NBUF > 5 ? BN * GR : 1];
+    auto tile_buf = [&](int u) __attribute__((always_inline)) -> uint4* {
+        return u == 0 ? bt0 : u == 1 ? bt1 : u == 2 ? bt2 : u == 3 ? bt3 : u == 4 ? bt4 : bt5;
+    };
     __shared__ __align__(16) float scores[2][BN * LDQ];
     // histogram bins of each consumer's pool selections: as many as the LDS
     // left over allows (at most 1024)
-    constexpr int kLdsBytes = 160 * 1024;
     constexpr int USED = NBUF * BN * GR * 16 + 2 * BN * LDQ * 4;
     constexpr int NBINS = !S::mem_queues                             ? 1
                           : USED + S::NC * 1024 * 4 <= kLdsBytes     ? 1024
@@ -911,9 +930,21 @@ knn_fused(FusedArgs args) {
                 row = row < c1 ? row : c1 - 1;
                 src = xb + row * row_bytes + lcc[t] * 16;
             }
-            uint4* dst = &btile[buf][(wave + t * kProducers) * 64];
+            uint4* dst = tile_buf(buf) + (wave + t * kProducers) * 64;
             if constexpr (VEC) {
-                __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)dst, 16, 0, 0);
+                // Direct global-to-LDS load (lane i writes 16 bytes at M0 + 16 i).
+                // Issued from asm so that the compiler's wait insertion does
+                // not see an LDS write in flight: it would otherwise wait for
+                // every such load before any later LDS read or barrier fence.
+                // It writes no register; its completion is waited for by the
+                // explicit vmcnt waits of the step loop (producers issue no
+                // other vector memory operations there).
+                const uint32_t m0 =
+                    __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_ptr_t)dst);
+                asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+                             :
+                             : "v"(src), "s"(m0)
+                             : "memory", "m0");
             } else {
                 dst[lane] = load_granule<Op, false>(xb + row * row_bytes, lcc[t], args.valid, true);
             }
@@ -934,79 +965,101 @@ knn_fused(FusedArgs args) {
 #pragma unroll
             for (int s4 = 0; s4 < S4; ++s4) areg[qb][s4] = load_granule<Op, VEC>(row, 4 * s4 + lh, args.valid, ok);
         }
-        if (nsteps > 0) load_tile(c0, 0);
-        if (NBUF == 3 && nsteps > 1) {
-            load_tile(c0 + BN, 1);
-            __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW>());  // tile 0 has landed
-        } else {
+        // the A operands have landed before any tile load is issued, so no
+        // wait in the step loop has to cover them
+        __builtin_amdgcn_s_waitcnt(0);
+        // Step barrier of the kernel: LDS writes (scores) complete, no LDS
+        // access crosses it, and -- unlike a fence -- the tile loads in flight
+        // are not waited for.
+        auto step_barrier = [&]() __attribute__((always_inline)) {
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        };
+        // The first AHEAD tiles, then wait for tile 0 only.
+#pragma unroll
+        for (int t = 0; t < AHEAD; ++t)
+            if (t < nsteps) load_tile(c0 + t * BN, t);
+        if (nsteps >= AHEAD)
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm<(AHEAD - 1) * LPW>());
+        else
             __builtin_amdgcn_s_waitcnt(0);
-        }
         __syncthreads();
-        for (int64_t s = 0; s <= nsteps; ++s) {
-            if (s < nsteps) {
-                const int64_t ahead = s + NBUF - 1;
-                const uint4* bt = btile[s % NBUF];
-                // All B granules of the step first, so that LDS latency
-                // overlaps the matrix work of earlier granules.
-                uint4 b[S4][DPB];
+        // Step s reads buffer s % NBUF and loads tile s + AHEAD into buffer
+        // (s + AHEAD) % NBUF, which step s - 1 read before the last barrier.
+        // The loop is unrolled NBUF times so that every buffer is named
+        // statically.
+        auto produce = [&](int64_t s, int u) __attribute__((always_inline)) {
+            const uint4* bt = tile_buf(u);
+            // All B granules of the step first, so that LDS latency
+            // overlaps the matrix work of earlier granules.
+            uint4 b[S4][DPB];
 #pragma unroll
-                for (int s4 = 0; s4 < S4; ++s4)
+            for (int s4 = 0; s4 < S4; ++s4)
 #pragma unroll
-                    for (int db = 0; db < DPB; ++db) {
-                        const int j = (dg * DPB + db) * 16 + li;
-                        b[s4][db] = bt[j * GR + ((4 * s4 + lh) ^ (j & SW))];
-                    }
-                // SK independent accumulators per output block (split over
-                // the granule steps) keep at least four MFMA chains in flight.
-                floatx4 acc[SK][QPB][DPB];
+                for (int db = 0; db < DPB; ++db) {
+                    const int j = (dg * DPB + db) * 16 + li;
+                    b[s4][db] = bt[j * GR + ((4 * s4 + lh) ^ (j & SW))];
+                }
+            // SK independent accumulators per output block (split over the
+            // granule steps) keep at least four MFMA chains in flight.
+            floatx4 acc[SK][QPB][DPB];
 #pragma unroll
-                for (int kk = 0; kk < SK; ++kk)
-#pragma unroll
-                    for (int qb = 0; qb < QPB; ++qb)
-#pragma unroll
-                        for (int db = 0; db < DPB; ++db) acc[kk][qb][db] = floatx4{0.f, 0.f, 0.f, 0.f};
-                // The tile loads two steps ahead are issued between the two
-                // halves of the matrix work, so their issue cost hides under it.
-                constexpr int H = S4 / 2;
-#pragma unroll
-                for (int s4 = 0; s4 < H; ++s4)
-#pragma unroll
-                    for (int qb = 0; qb < QPB; ++qb)
-#pragma unroll
-                        for (int db = 0; db < DPB; ++db)
-                            acc[s4 % SK][qb][db] = Op::mma(acc[s4 % SK][qb][db], areg[qb][s4], b[s4][db]);
-                __builtin_amdgcn_sched_barrier(0);
-                if (ahead < nsteps) load_tile(c0 + ahead * BN, (int)(ahead % NBUF));
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int s4 = H; s4 < S4; ++s4)
-#pragma unroll
-                    for (int qb = 0; qb < QPB; ++qb)
-#pragma unroll
-                        for (int db = 0; db < DPB; ++db)
-                            acc[s4 % SK][qb][db] = Op::mma(acc[s4 % SK][qb][db], areg[qb][s4], b[s4][db]);
-                // D[i][j] of a 16x16 block sits in lane j + 16*(i/4), element
-                // i%4: one 16-byte store of queries 4*lh .. 4*lh+3 of column j.
-                float* slot = scores[s & 1];
+            for (int kk = 0; kk < SK; ++kk)
 #pragma unroll
                 for (int qb = 0; qb < QPB; ++qb)
 #pragma unroll
-                    for (int db = 0; db < DPB; ++db) {
-                        floatx4 v = acc[0][qb][db];
+                    for (int db = 0; db < DPB; ++db) acc[kk][qb][db] = floatx4{0.f, 0.f, 0.f, 0.f};
+            // The tile loads AHEAD steps ahead are issued between the two
+            // halves of the matrix work, so their issue cost hides under it.
+            constexpr int H = S4 / 2;
 #pragma unroll
-                        for (int kk = 1; kk < SK; ++kk) v += acc[kk][qb][db];
-                        const int j = (dg * DPB + db) * 16 + li;
-                        *reinterpret_cast<floatx4*>(&slot[j * LDQ + (qg * QPB + qb) * 16 + 4 * lh]) = v;
-                    }
-                // next step's tile (and this step's score stores) must have
-                // landed; with three buffers the loads of the tile after it
-                // may stay in flight
-                if (NBUF == 3 && ahead < nsteps)
-                    __builtin_amdgcn_s_waitcnt(waitcnt_vm<LPW>());
-                else
-                    __builtin_amdgcn_s_waitcnt(0);
+            for (int s4 = 0; s4 < H; ++s4)
+#pragma unroll
+                for (int qb = 0; qb < QPB; ++qb)
+#pragma unroll
+                    for (int db = 0; db < DPB; ++db)
+                        acc[s4 % SK][qb][db] = Op::mma(acc[s4 % SK][qb][db], areg[qb][s4], b[s4][db]);
+            __builtin_amdgcn_sched_barrier(0);
+            const bool issue = s + AHEAD < nsteps;
+            if (issue) load_tile(c0 + (s + AHEAD) * BN, (u + AHEAD) % NBUF);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s4 = H; s4 < S4; ++s4)
+#pragma unroll
+                for (int qb = 0; qb < QPB; ++qb)
+#pragma unroll
+                    for (int db = 0; db < DPB; ++db)
+                        acc[s4 % SK][qb][db] = Op::mma(acc[s4 % SK][qb][db], areg[qb][s4], b[s4][db]);
+            // D[i][j] of a 16x16 block sits in lane j + 16*(i/4), element
+            // i%4: one 16-byte store of queries 4*lh .. 4*lh+3 of column j.
+            float* slot = scores[s & 1];
+#pragma unroll
+            for (int qb = 0; qb < QPB; ++qb)
+#pragma unroll
+                for (int db = 0; db < DPB; ++db) {
+                    floatx4 v = acc[0][qb][db];
+#pragma unroll
+                    for (int kk = 1; kk < SK; ++kk) v += acc[kk][qb][db];
+                    const int j = (dg * DPB + db) * 16 + li;
+                    *reinterpret_cast<floatx4*>(&slot[j * LDQ + (qg * QPB + qb) * 16 + 4 * lh]) = v;
+                }
+            // the next step's tile must have landed (this wave's part of it;
+            // the barrier covers the other producers); the AHEAD - 1 tiles
+            // after it stay in flight
+            if (issue)
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm<(AHEAD - 1) * LPW>());
+            else
+                __builtin_amdgcn_s_waitcnt(0);
+        };
+#pragma unroll 1
+        for (int64_t s0 = 0; s0 <= nsteps; s0 += NBUF) {
+#pragma unroll
+            for (int u = 0; u < NBUF; ++u) {
+                const int64_t s = s0 + u;
+                if (s <= nsteps) {
+                    if (s < nsteps) produce(s, u);
+                    step_barrier();
+                }
             }
-            __syncthreads();
         }
     } else {
         // ------------------------------------------------ consumer
@@ -1103,7 +1156,9 @@ knn_fused(FusedArgs args) {
                     }
                 }
             }
-            __syncthreads();
+            // the producers' step barrier (LDS only: the consumers' own
+            // global loads and pool appends are not waited for here)
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
         }
         sel.finish();
         if constexpr (!S::mem_queues) {
