@@ -938,10 +938,15 @@ knn_fused(FusedArgs args) {
                 // every such load before any later LDS read or barrier fence.
                 // It writes no register; its completion is waited for by the
                 // explicit vmcnt waits of the step loop (producers issue no
-                // other vector memory operations there).
+                // other vector memory operations there).  An LDS DMA load
+                // needs one wait state after the write of M0 (the s_nop; the
+                // compiler inserts the same for its own such loads).  M0 is
+                // reserved to the compiler, which sets it before each of its
+                // own uses; the kernel's generated code has no M0 user but
+                // these loads.
                 const uint32_t m0 =
                     __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_ptr_t)dst);
-                asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+                asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
                              :
                              : "v"(src), "s"(m0)
                              : "memory", "m0");
