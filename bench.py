@@ -302,6 +302,7 @@ def ivfpq_section(api, synth, torch):
                            "ms_min": round(dmin * 1e3, 3),
                            "qps": round(nq / dt, 1), "recall_at_10": r1,
                            "ten_intersection": r2})
+    scan_options = scan_options_section(api, torch, ix, xq, w, sizes, probe)
     graph = graph_section(api, torch, ix, xb, w, t_train + t_add)
     learned = learned_probe_section(api, synth, torch, ix, xb, xq, w, recalls)
     serving = serving_section(api, synth, torch, ix, xb, xq, w, learned)
@@ -310,6 +311,7 @@ def ivfpq_section(api, synth, torch):
     best = [c for c in curve if c["recall_at_10"] >= 0.9]
     best_rr = sorted((c for c in rerank if c["recall_at_10"] >= 0.9), key=lambda c: -c["qps"])
     return {"learned_probe": learned, "serving": serving, "knn_graph": graph,
+            "scan_options": scan_options,
             "workload": "10,000,000 x 128 mixture, nlist 4096, PQ 16 x 8 bit, 10,000 queries, "
                         "k = 100 (ADC) / k = 10 after exact re-rank of R, "
                         "train 500,000 rows x 20 iterations",
@@ -321,6 +323,63 @@ def ivfpq_section(api, synth, torch):
             "qps_at_recall10_0.9_rerank": best_rr[0]["qps"] if best_rr else None,
             "rerank_setting_at_recall10_0.9": ({"nprobe": best_rr[0]["nprobe"],
                                                  "R": best_rr[0]["R"]} if best_rr else None)}
+
+
+def scan_options_section(api, torch, ix, xq, w, sizes, probe):
+    """The list scan with its options side by side at k = 100: the automatic
+    grouping (as many probed lists per workgroup as keep 2048+ workgroups),
+    fixed groups of 16 lists, the per-query fused scan (one workgroup per
+    query over all its lists, Section 5.3), and 16-bit lookup tables; scan
+    kernel time and algorithmic bytes (codes + stored term 1) per second."""
+    nq, k = xq.shape[0], w["k"]
+    rows = []
+    for nprobe in (8, 32, 128):
+        alg = int(sizes[probe[:, :nprobe]].sum()) * (w["M"] + 4)
+        for label, lut, group in (("automatic", "fp32", 0), ("groups of 16", "fp32", 16),
+                                  ("per-query fused", "fp32", -1), ("fp16 tables", "fp16", 0)):
+            ix.set_scan_options(lut, group)
+            api.profile_enable(True)
+            dt, dmin = _timed(torch, lambda: ix.search(xq, k, nprobe))
+            api.profile_enable(False)
+            name = "ivf_scan_lut16" if lut == "fp16" else "ivf_scan"
+            ms, n = api.profile_read(name)
+            scan_s = ms / max(n, 1) / 1e3
+            rows.append({"nprobe": nprobe, "variant": label, "search_ms": round(dt * 1e3, 3),
+                         "qps": round(nq / dt, 1), "scan_ms": round(scan_s * 1e3, 3),
+                         "scan_GB/s": round(alg / scan_s / 1e9, 1) if scan_s > 0 else None})
+    ix.set_scan_options("fp32", 0)
+    return {"k": k, "rows": rows}
+
+
+def host_db_section(api, synth, torch):
+    """Exact search against a database held in pinned host memory, streamed
+    in chunks (copies overlapping the fused search of the previous chunk),
+    next to the same search on a device-resident copy: the 10,000,000 x 128
+    mixture of the IVFADC workload (5.1 GB), k = 10."""
+    w = synth.ivfpq_workload(nq=10_000)
+    xb_h = torch.from_numpy(w["xb"])
+    pinned = torch.empty(xb_h.shape, dtype=torch.float32, pin_memory=True)
+    pinned.copy_(xb_h)
+    del xb_h
+    xq = torch.from_numpy(w["xq"]).cuda()
+    gb = pinned.numel() * 4 / 1e9
+    # plain host-to-device copy rate of the same bytes
+    dev = torch.empty_like(pinned, device="cuda")
+    dt_copy, _ = _timed(torch, lambda: dev.copy_(pinned, non_blocking=True), 3)
+    rows = []
+    for nq in (1_000, 10_000):
+        q = xq[:nq].contiguous()
+        dt_dev, _ = _timed(torch, lambda: api.knn_search(q, dev, 10), 3)
+        for chunk in (1 << 20, 1 << 21):
+            progress(f"host db: nq {nq}, chunk {chunk}")
+            dt, dmin = _timed(torch, lambda: api.knn_search_host(q, pinned, 10, "l2", chunk), 3)
+            rows.append({"nq": nq, "chunk_rows": chunk, "ms": round(dt * 1e3, 1),
+                         "ms_min": round(dmin * 1e3, 1), "device_resident_ms": round(dt_dev * 1e3, 1),
+                         "effective_GB/s": round(gb / dt, 1)})
+    del dev, pinned
+    torch.cuda.empty_cache()
+    return {"workload": "10,000,000 x 128 float32 mixture in pinned host memory (5.12 GB), k = 10",
+            "h2d_copy_GB/s": round(gb / dt_copy, 1), "rows": rows}
 
 
 def graph_section(api, torch, ix, xb, w, build_s):
@@ -646,7 +705,8 @@ def main() -> int:
         return 0
     if args.section:
         fns = {"small_exact": small_exact_section, "kselect": kselect_section,
-               "ivfpq": ivfpq_section, "lowp": lowp_section, "ivf_large": ivf_large_run}
+               "ivfpq": ivfpq_section, "lowp": lowp_section, "ivf_large": ivf_large_run,
+               "host_db": host_db_section}
         print(json.dumps({args.section: fns[args.section](api, synth, torch)}), flush=True)
         return 0
 
@@ -735,7 +795,8 @@ def main() -> int:
     torch.cuda.empty_cache()
     if not args.skip_extra:
         sections = [("small_exact", small_exact_section), ("kselect", kselect_section),
-                    ("ivfpq", ivfpq_section), ("lowp", lowp_section)]
+                    ("ivfpq", ivfpq_section), ("lowp", lowp_section),
+                    ("host_db", host_db_section)]
         if not args.skip_large:
             sections.append(("ivf_large", ivf_large_run))
         for name, fn in sections:

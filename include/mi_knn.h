@@ -495,9 +495,10 @@ int32_t mk_ivfpq_dim(const mk_ivfpq* index);
  *                  (FP32 tables of M <= 64 fill at most 64 KiB of LDS).
  *                  Entries must satisfy |2 term3| < 65504.
  *   lists_per_group  probed lists of one query scanned by one workgroup:
- *                  0 (default) chosen from the launch size (enough
- *                  workgroups to fill the chip, at most 16 lists each), -1
- *                  all of a query's lists (the per-query fused scan of
+ *                  0 (default) chosen from the launch size: as many
+ *                  lists per workgroup as keep 2048 or more workgroups
+ *                  (all of a query's lists from about 2048 queries on),
+ *                  -1 all of a query's lists (the per-query fused scan of
  *                  Section 5.3), or a count 1..1024.
  * Results do not depend on lists_per_group (candidates are keyed by
  * (distance, id)).  MK_ERR_UNSUPPORTED for another precision.

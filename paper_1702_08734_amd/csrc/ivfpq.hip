@@ -765,11 +765,14 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
     }
 }
 
-// Lists per workgroup: enough workgroups for the chip (about 8 per CU)
-// while sharing each query's table over as many lists as possible.
-int32_t scan_group(int64_t total_probes) {
+// Lists per workgroup: as many as keep the launch at 2048+ workgroups
+// (about 8 per CU), so each query's table is staged once for as many lists
+// as possible and fewer partial lists reach the merge; with enough queries
+// every query's lists go to one workgroup (measured on 10^7 x 128, nprobe
+// 128: 11.3 ms per-query against 15.6 ms for groups of 16).
+int32_t scan_group(int64_t total_probes, int32_t nprobe) {
     const int64_t g = total_probes / 2048;
-    return (int32_t)(g < 1 ? 1 : g > 16 ? 16 : g);
+    return (int32_t)(g < 1 ? 1 : g > nprobe ? nprobe : g);
 }
 
 // The index's choice of lists per workgroup for nq queries probing up to
@@ -778,7 +781,7 @@ int32_t scan_group(int64_t total_probes) {
 int32_t scan_group_of(const mk_ivfpq* ix, int64_t nq, int32_t nprobe, int32_t auto_probes) {
     if (ix->lists_per_group < 0) return nprobe;
     if (ix->lists_per_group > 0) return ix->lists_per_group < nprobe ? ix->lists_per_group : nprobe;
-    return scan_group(nq * (int64_t)auto_probes);
+    return scan_group(nq * (int64_t)auto_probes, nprobe);
 }
 
 mk_status launch_scan(const float* term3, const float* t1e, const float* cd, const int64_t* ci,
