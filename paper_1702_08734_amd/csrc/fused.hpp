@@ -150,19 +150,22 @@ struct MultiSelect {
     // false means no candidate.  A query whose scores all lose to its current
     // threshold is skipped after one compare per lane.
     __device__ __forceinline__ void offer(const float (&score)[QW], uint32_t idx, bool ok) {
-        // one compare per query into a wave mask, one test of their union:
-        // the common case (no query takes anything) costs no per-query branch
+        // one compare per query straight into a wave mask, one test of
+        // their union with the lanes in range: the common case (no query
+        // takes anything) costs two vector and one scalar instruction per
+        // query and no per-query branch
+        const uint64_t okm = __builtin_amdgcn_ballot_w64(ok);
         uint64_t cand[QW], any = 0;
 #pragma unroll
         for (int q = 0; q < QW; ++q) {
-            cand[q] = __ballot(ok && score[q] <= kf[q]);
+            cand[q] = __builtin_amdgcn_ballot_w64(score[q] <= kf[q]);
             any |= cand[q];
         }
-        if (!any) return;
+        if (!(any & okm)) return;
         uint32_t full = 0;
 #pragma unroll
         for (int q = 0; q < QW; ++q) {
-            if (cand[q]) {
+            if (cand[q] & okm) {
                 const uint64_t key = ok ? make_key(score[q], idx) : kSentinel;
                 const uint64_t kth = ((uint64_t)kh[q] << 32) | kl[q];
                 const bool take = key < kth;
@@ -242,12 +245,13 @@ __device__ __forceinline__ int wave_inclusive_sum(int v) {
 // it.  The level-0 histogram also yields the rank points published for the
 // other chunks (see above).  Queries at or beyond nvalid never take
 // candidates and are never written.
-template <int KR, int QW, int NB>
+template <int KR, int QW, int NB, int RB = 16>
 struct PoolSelect {
     static constexpr int kQueries = QW;
     static constexpr int KS = 64 * KR;
     static constexpr int CAP = 2 * KS;  // pool capacity in keys
     static constexpr int PRG = CAP / 64;
+    static constexpr int kRB = PRG < RB ? PRG : RB;  // pool rows per lane loaded together
     static constexpr int NBL = NB / 64;  // bins per lane in a scan
     static constexpr int LOGNB = NB == 1024 ? 10 : NB == 512 ? 9 : NB == 256 ? 8 : 7;
     static_assert(NB == 1024 || NB == 512 || NB == 256 || NB == 128, "bins");
@@ -364,14 +368,25 @@ struct PoolSelect {
         if (n <= target) return;
         // the appends of every lane of this wave are visible to its loads
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        // Each pass loads the pool in batches of kRB rows per lane, issued
+        // together (indices clamped into the pool, so no load is guarded):
+        // a cut's latency is a few round trips, not one per row.
+        auto batch = [&](int r0, uint64_t (&kk)[kRB]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int b = 0; b < kRB; ++b) {
+                const int i = (r0 + b) * 64 + lane;
+                kk[b] = pp[i < n ? i : n - 1];
+            }
+        };
         uint64_t lo = kSentinel, hi = 0;
-#pragma unroll 8
-        for (int r = 0; r < PRG; ++r) {
-            const int i = r * 64 + lane;
-            if (i < n) {
-                const uint64_t k = pp[i];
-                lo = umin64(lo, k);
-                hi = umax64(hi, k);
+#pragma unroll 1
+        for (int r0 = 0; r0 * 64 < n; r0 += kRB) {
+            uint64_t kk[kRB];
+            batch(r0, kk);
+#pragma unroll
+            for (int b = 0; b < kRB; ++b) {
+                lo = umin64(lo, kk[b]);
+                hi = umax64(hi, kk[b]);
             }
         }
         lo = wave_min64(lo);
@@ -384,12 +399,15 @@ struct PoolSelect {
             const uint64_t range = hi - lo;
             const int bits = range ? 64 - __builtin_clzll(range) : 0;
             const int shift = bits > LOGNB ? bits - LOGNB : 0;
-#pragma unroll 8
-            for (int r = 0; r < PRG; ++r) {
-                const int i = r * 64 + lane;
-                if (i < n) {
-                    const uint64_t k = pp[i];
-                    if (k >= lo && k <= hi) atomicAdd(&hist[(uint32_t)((k - lo) >> shift)], 1u);
+#pragma unroll 1
+            for (int r0 = 0; r0 * 64 < n; r0 += kRB) {
+                uint64_t kk[kRB];
+                batch(r0, kk);
+#pragma unroll
+                for (int b = 0; b < kRB; ++b) {
+                    const uint64_t k = kk[b];
+                    if ((r0 + b) * 64 + lane < n && k >= lo && k <= hi)
+                        atomicAdd(&hist[(uint32_t)((k - lo) >> shift)], 1u);
                 }
             }
             __builtin_amdgcn_s_waitcnt(waitcnt_lgkm0());
@@ -428,20 +446,26 @@ struct PoolSelect {
             hi = nhi;
         }
         // keep the keys at or below the cut, packed at the front
+        // (in place: a batch's stores land at or below its own rows, after
+        // its loads, and below every row of the later batches)
         int kept = 0;
         uint64_t top = 0;
-#pragma unroll 8
-        for (int r = 0; r < PRG; ++r) {
-            const int i = r * 64 + lane;
-            const uint64_t k = i < n ? pp[i] : kSentinel;
-            const bool keep = k <= cut;
-            const uint64_t bal = __ballot(keep);
-            const int pos = kept + (int)__builtin_amdgcn_mbcnt_hi(
-                                        (uint32_t)(bal >> 32),
-                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            if (keep) pp[pos] = k;
-            top = keep ? umax64(top, k) : top;
-            kept += __popcll(bal);
+#pragma unroll 1
+        for (int r0 = 0; r0 * 64 < n; r0 += kRB) {
+            uint64_t kk[kRB];
+            batch(r0, kk);
+#pragma unroll
+            for (int b = 0; b < kRB; ++b) {
+                const uint64_t k = kk[b];
+                const bool keep = (r0 + b) * 64 + lane < n && k <= cut;
+                const uint64_t bal = __ballot(keep);
+                const int pos = kept + (int)__builtin_amdgcn_mbcnt_hi(
+                                            (uint32_t)(bal >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                if (keep) pp[pos] = k;
+                top = keep ? umax64(top, k) : top;
+                kept += __popcll(bal);
+            }
         }
         top = wave_max64(top);
 #pragma unroll
@@ -459,17 +483,19 @@ struct PoolSelect {
     __device__ __forceinline__ void offer(const float (&score)[QW], uint32_t idx, bool ok) {
         uint32_t full = 0;
         const int lane = lane_id();
-        // one compare per query into a wave mask, one test of their union
+        // one compare per query straight into a wave mask, one test of
+        // their union with the lanes in range
+        const uint64_t okm = __builtin_amdgcn_ballot_w64(ok);
         uint64_t cand[QW], any = 0;
 #pragma unroll
         for (int q = 0; q < QW; ++q) {
-            cand[q] = __ballot(ok && score[q] <= kf[q]);
+            cand[q] = __builtin_amdgcn_ballot_w64(score[q] <= kf[q]);
             any |= cand[q];
         }
-        if (!any) return;
+        if (!(any & okm)) return;
 #pragma unroll
         for (int q = 0; q < QW; ++q) {
-            if (cand[q]) {
+            if (cand[q] & okm) {
                 const uint64_t key = ok ? make_key(score[q], idx) : kSentinel;
                 const uint64_t kth = ((uint64_t)kh[q] << 32) | kl[q];
                 const bool take = key < kth;
@@ -879,6 +905,16 @@ knn_fused(FusedArgs args) {
     auto tile_buf = [&](int u) __attribute__((always_inline)) -> uint4* {
         return u == 0 ? bt0 : u == 1 ? bt1 : u == 2 ? bt2 : u == 3 ? bt3 : u == 4 ? bt4 : bt5;
     };
+    // LDS byte address of buffer u (each array's own address, a constant,
+    // so no generic-pointer conversion is left for the loads to pay)
+    auto tile_lds = [&](int u) __attribute__((always_inline)) -> uint32_t {
+        return u == 0   ? (uint32_t)(uintptr_t)(lds_ptr_t)bt0
+               : u == 1 ? (uint32_t)(uintptr_t)(lds_ptr_t)bt1
+               : u == 2 ? (uint32_t)(uintptr_t)(lds_ptr_t)bt2
+               : u == 3 ? (uint32_t)(uintptr_t)(lds_ptr_t)bt3
+               : u == 4 ? (uint32_t)(uintptr_t)(lds_ptr_t)bt4
+                        : (uint32_t)(uintptr_t)(lds_ptr_t)bt5;
+    };
     __shared__ __align__(16) float scores[2][BN * LDQ];
     // histogram bins of each consumer's pool selections: as many as the LDS
     // left over allows (at most 1024)
@@ -895,12 +931,14 @@ knn_fused(FusedArgs args) {
     const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)args.nqb * args.nchunks);
     const int64_t chunk = logical / args.nqb;
     const int64_t qblk = logical % args.nqb;
-    const int wave = threadIdx.x >> 6;
+    // wave-uniform, and known to be so (scalar registers, scalar branches)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = lane_id();
     const int64_t q0 = qblk * BQ;
     const int64_t c0 = chunk * args.chunk_len;
     const int64_t c1 = c0 + args.chunk_len < args.nb ? c0 + args.chunk_len : args.nb;
-    const int64_t nsteps = c1 > c0 ? (c1 - c0 + BN - 1) / BN : 0;
+    // 32-bit step counters (scalar compares): a chunk has fewer than 2^31 rows
+    const int nsteps = c1 > c0 ? (int)((c1 - c0 + BN - 1) / BN) : 0;
     const int64_t row_bytes = (int64_t)args.stride * Op::BYTES;
     const unsigned char* xb = static_cast<const unsigned char*>(args.xb);
 
@@ -920,38 +958,46 @@ knn_fused(FusedArgs args) {
         lcc[t] = cc;
         loff[t] = (int32_t)(j * row_bytes + cc * 16);
     }
-    auto load_tile = [&](int64_t t0, int buf) {
-        const bool tail = t0 + BN > c1;  // wave-uniform
+    // Direct global-to-LDS load of 16 bytes per lane (lane i writes at LDS
+    // byte address m0 + 16 i).  Issued from asm so that the compiler's wait
+    // insertion does not see an LDS write in flight: it would otherwise wait
+    // for every such load before any later LDS read or barrier fence.  It
+    // writes no register; its completion is waited for by the explicit
+    // vmcnt waits of the step loop (producers issue no other vector memory
+    // operations there).  An LDS DMA load needs one wait state after the
+    // write of M0 (the s_nop; the compiler inserts the same for its own such
+    // loads).  M0 is reserved to the compiler, which sets it before each of
+    // its own uses; the kernel's generated code has no M0 user but these
+    // loads.
+    auto dma16 = [&](const unsigned char* src, uint32_t m0) __attribute__((always_inline)) {
+        asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                     :
+                     : "v"(src), "s"(m0)
+                     : "memory", "m0");
+    };
+    auto load_tile = [&](int64_t t0, int buf) __attribute__((always_inline)) {
+        const uint32_t base = tile_lds(buf) + (uint32_t)(wave * 64 * 16);
+        if (t0 + BN <= c1) {  // wave-uniform: a whole tile of the chunk
 #pragma unroll
-        for (int t = 0; t < LPW; ++t) {
-            int64_t row = t0 + lrow[t];
-            const unsigned char* src = xb + t0 * row_bytes + loff[t];
-            if (tail) {
-                row = row < c1 ? row : c1 - 1;
-                src = xb + row * row_bytes + lcc[t] * 16;
+            for (int t = 0; t < LPW; ++t) {
+                if constexpr (VEC) {
+                    dma16(xb + t0 * row_bytes + loff[t], base + (uint32_t)(t * kProducers * 64 * 16));
+                } else {
+                    tile_buf(buf)[(wave + t * kProducers) * 64 + lane] =
+                        load_granule<Op, false>(xb + (t0 + lrow[t]) * row_bytes, lcc[t], args.valid, true);
+                }
             }
-            uint4* dst = tile_buf(buf) + (wave + t * kProducers) * 64;
-            if constexpr (VEC) {
-                // Direct global-to-LDS load (lane i writes 16 bytes at M0 + 16 i).
-                // Issued from asm so that the compiler's wait insertion does
-                // not see an LDS write in flight: it would otherwise wait for
-                // every such load before any later LDS read or barrier fence.
-                // It writes no register; its completion is waited for by the
-                // explicit vmcnt waits of the step loop (producers issue no
-                // other vector memory operations there).  An LDS DMA load
-                // needs one wait state after the write of M0 (the s_nop; the
-                // compiler inserts the same for its own such loads).  M0 is
-                // reserved to the compiler, which sets it before each of its
-                // own uses; the kernel's generated code has no M0 user but
-                // these loads.
-                const uint32_t m0 =
-                    __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_ptr_t)dst);
-                asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
-                             :
-                             : "v"(src), "s"(m0)
-                             : "memory", "m0");
-            } else {
-                dst[lane] = load_granule<Op, false>(xb + row * row_bytes, lcc[t], args.valid, true);
+        } else {
+#pragma unroll
+            for (int t = 0; t < LPW; ++t) {
+                int64_t row = t0 + lrow[t];
+                row = row < c1 ? row : c1 - 1;
+                if constexpr (VEC) {
+                    dma16(xb + row * row_bytes + lcc[t] * 16, base + (uint32_t)(t * kProducers * 64 * 16));
+                } else {
+                    tile_buf(buf)[(wave + t * kProducers) * 64 + lane] =
+                        load_granule<Op, false>(xb + row * row_bytes, lcc[t], args.valid, true);
+                }
             }
         }
     };
@@ -982,7 +1028,7 @@ knn_fused(FusedArgs args) {
         // The first AHEAD tiles, then wait for tile 0 only.
 #pragma unroll
         for (int t = 0; t < AHEAD; ++t)
-            if (t < nsteps) load_tile(c0 + t * BN, t);
+            if (t < nsteps) load_tile(c0 + (int64_t)t * BN, t);
         if (nsteps >= AHEAD)
             __builtin_amdgcn_s_waitcnt(waitcnt_vm<(AHEAD - 1) * LPW>());
         else
@@ -992,7 +1038,7 @@ knn_fused(FusedArgs args) {
         // (s + AHEAD) % NBUF, which step s - 1 read before the last barrier.
         // The loop is unrolled NBUF times so that every buffer is named
         // statically.
-        auto produce = [&](int64_t s, int u) __attribute__((always_inline)) {
+        auto produce = [&](int s, int u) __attribute__((always_inline)) {
             const uint4* bt = tile_buf(u);
             // All B granules of the step first, so that LDS latency
             // overlaps the matrix work of earlier granules.
@@ -1025,7 +1071,7 @@ knn_fused(FusedArgs args) {
                         acc[s4 % SK][qb][db] = Op::mma(acc[s4 % SK][qb][db], areg[qb][s4], b[s4][db]);
             __builtin_amdgcn_sched_barrier(0);
             const bool issue = s + AHEAD < nsteps;
-            if (issue) load_tile(c0 + (s + AHEAD) * BN, (u + AHEAD) % NBUF);
+            if (issue) load_tile(c0 + (int64_t)(s + AHEAD) * BN, (u + AHEAD) % NBUF);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int s4 = H; s4 < S4; ++s4)
@@ -1056,10 +1102,10 @@ knn_fused(FusedArgs args) {
                 __builtin_amdgcn_s_waitcnt(0);
         };
 #pragma unroll 1
-        for (int64_t s0 = 0; s0 <= nsteps; s0 += NBUF) {
+        for (int s0 = 0; s0 <= nsteps; s0 += NBUF) {
 #pragma unroll
             for (int u = 0; u < NBUF; ++u) {
-                const int64_t s = s0 + u;
+                const int s = s0 + u;
                 if (s <= nsteps) {
                     if (s < nsteps) produce(s, u);
                     step_barrier();
@@ -1071,7 +1117,10 @@ knn_fused(FusedArgs args) {
         // score = ||y||^2 - 2 q.y (L2) or -q.y (inner product); ||x||^2 is the
         // same for every candidate of a query and does not change its rank.
         // Scaled formats multiply q.y by the query's and the row's 1/scale.
-        const int cw = wave - kProducers;
+        // The pool selectors take the consumer index from the thread id
+        // (vector registers): made scalar, their wave-uniform state outgrows
+        // the scalar registers and spills.
+        const int cw = S::mem_queues ? (int)(threadIdx.x >> 6) - kProducers : wave - kProducers;
         using Sel = typename std::conditional<S::mem_queues, PoolSelect<KR, QW, NBINS>,
                                               MultiSelect<KR, T, QW>>::type;
         Sel sel;
@@ -1101,8 +1150,8 @@ knn_fused(FusedArgs args) {
         }
         // bound exchanges: often early, while the queues fill (steps 0, 4, 8,
         // 16, 32), then every 64 steps
-        int64_t next_x = args.bound ? 0 : nsteps + 1;
-        for (int64_t s = 0; s <= nsteps; ++s) {
+        int next_x = args.bound ? 0 : nsteps + 1;
+        for (int s = 0; s <= nsteps; ++s) {
             if (s == next_x) {
                 next_x = s == 0 ? 4 : s < 64 ? 2 * s : s + 64;
                 if constexpr (S::mem_queues)
@@ -1123,7 +1172,7 @@ knn_fused(FusedArgs args) {
                     sel.refine_pools(batch);
                 }
                 const float* slot = scores[(s - 1) & 1];
-                const int64_t g = c0 + (s - 1) * BN + lane;
+                const int64_t g = c0 + (int64_t)(s - 1) * BN + lane;
                 const bool ok = g < c1;
                 const float ynv = ynext, ysv = ysnext;
                 if (g + BN < c1) {
@@ -1202,16 +1251,17 @@ inline mk_status clear_bounds(int KR, uint32_t* bound, int64_t nq, int64_t nchun
 }
 
 // Chunking of the database.  Chunks of a query that run at the same time
-// each fill their queue before shared bounds can help, so long queues get
-// fewer, longer chunks: about 4 workgroups per CU for queues of 512+ entries,
-// 16 otherwise, chunks of at least 32 queue lengths, at most kMaxRankChunks
+// each fill their queue before shared bounds can help, and a pool's
+// insertions grow with the number of chunks, so long queues get few, long
+// chunks: about 2 workgroups per CU for queues of 512+ entries, 16
+// otherwise, chunks of at least 32 queue lengths, at most kMaxRankChunks
 // chunks, and among chunk counts within 25% of that target the one whose
 // last wave of workgroups is fullest.
 inline void plan_chunks(int64_t nq, int64_t nb, int BQ, int BN, int KS, int64_t* nqb,
                         int64_t* nchunks, int64_t* chunk_len) {
     constexpr int64_t kCUs = 256;
     *nqb = ceil_div(nq, BQ);
-    const int64_t target = (KS >= 512 ? 4 : 16) * kCUs;
+    const int64_t target = (KS >= 512 ? 2 : 16) * kCUs;
     const int64_t want = ceil_div(target, *nqb);
     int64_t max_by_len = nb / (32 * KS) > 1 ? nb / (32 * KS) : 1;
     if (max_by_len > kMaxRankChunks) max_by_len = kMaxRankChunks;

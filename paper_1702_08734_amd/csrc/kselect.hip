@@ -145,7 +145,9 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_pool(
     constexpr int U = 4;
     constexpr int NB = 512;
     constexpr int T = SelParams<KR>::T;
-    using Pool = PoolSelect<KR, 1, NB>;
+    // cuts load 8 pool rows per lane at a time: few registers, so that
+    // enough waves stream the input
+    using Pool = PoolSelect<KR, 1, NB, 8>;
     __shared__ float stage[kWavesPerBlock][4 * U][64];
     __shared__ uint32_t bins[kWavesPerBlock][NB];
     const int wave = threadIdx.x / 64;
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_pool(
 
     Pool pool;
     pool.init(k, pool_keys, 0, 1, nullptr, 1, bins[wave], drops);
-    auto offer = [&](float v, uint32_t i, bool ok) {
+    auto offer = [&](float v, uint32_t i, bool ok) __attribute__((always_inline)) {
         pool.refine_pools(false);  // room for the up to 64 keys one offer appends
         const float sc[1] = {LARGEST ? -v : v};
         pool.offer(sc, i, ok);
