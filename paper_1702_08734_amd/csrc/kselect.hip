@@ -136,6 +136,19 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_pass1(
 // radix selection inside the wave whenever it nears capacity (PoolSelect,
 // the fused search's selector).  At the end the pool is cut to 64 * KR keys,
 // which one WaveSelect pass sorts.
+//
+// Most of a segment would be offered early, while the pool's threshold is
+// still loose, so the threshold starts from a guess: the score of rank
+// about 1.5 k SN / L + 32 among the segment's first SN = 8192 scores (a
+// 512-bin histogram over their range), which about 1.5 k of the L scores
+// beat when the prefix is typical.  Values at or below the guess (and the
+// pool's own threshold) are appended in bulk: a lane counts its candidates
+// among its 16 values, a wave prefix sum places them, and each lane writes
+// its own.  The guess is no bound, so it is checked: when fewer than k
+// values were appended, fewer than k scores lie at or below it and the
+// segment is streamed again without it (the plain pool selection).
+// Otherwise the k best scores are all at or below it and the result is
+// exact.
 template <int KR, bool LARGEST>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_pool(
     const float* __restrict__ a, int64_t nrows, int64_t len, int32_t k, int32_t nseg,
@@ -144,6 +157,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_pool(
     unsigned long long* drops) {
     constexpr int U = 4;
     constexpr int NB = 512;
+    constexpr int SN = 8192;  // prefix that yields the guess
     constexpr int T = SelParams<KR>::T;
     // cuts load 8 pool rows per lane at a time: few registers, so that
     // enough waves stream the input
@@ -160,31 +174,102 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_pool(
     const int64_t hi = lo + seg_len < len ? lo + seg_len : len;
     const float* rp = a + row * len;
     uint64_t* pool_keys = pools + unit * Pool::CAP;
+    auto score = [&](float v) __attribute__((always_inline)) { return LARGEST ? -v : v; };
 
-    Pool pool;
-    pool.init(k, pool_keys, 0, 1, nullptr, 1, bins[wave], drops);
-    auto offer = [&](float v, uint32_t i, bool ok) __attribute__((always_inline)) {
-        pool.refine_pools(false);  // room for the up to 64 keys one offer appends
-        const float sc[1] = {LARGEST ? -v : v};
-        pool.offer(sc, i, ok);
-    };
     const bool aligned = (reinterpret_cast<uintptr_t>(rp + lo) & 15) == 0;
     const int64_t vec_end = aligned ? lo + ((hi - lo) / (256 * U)) * (256 * U) : lo;
-    for (int64_t e = lo; e < vec_end; e += 256 * U) {
-        float4 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            v[u] = *reinterpret_cast<const float4*>(rp + e + u * 256 + lane * 4);
-        const float th = pool.kf[0];
-        bool cand = false;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            cand |= (LARGEST ? -v[u].x : v[u].x) <= th;
-            cand |= (LARGEST ? -v[u].y : v[u].y) <= th;
-            cand |= (LARGEST ? -v[u].z : v[u].z) <= th;
-            cand |= (LARGEST ? -v[u].w : v[u].w) <= th;
+
+    // ---- the guess (aligned segments of at least 4 SN values)
+    float guess = INFINITY;
+    if (aligned && hi - lo >= 4 * (int64_t)SN) {
+        uint32_t omin = ~0u, omax = 0u;
+#pragma unroll 4
+        for (int t = 0; t < SN / 256; ++t) {
+            const float4 v = *reinterpret_cast<const float4*>(rp + lo + t * 256 + lane * 4);
+            const uint32_t o0 = float_order(score(v.x) + 0.f), o1 = float_order(score(v.y) + 0.f);
+            const uint32_t o2 = float_order(score(v.z) + 0.f), o3 = float_order(score(v.w) + 0.f);
+            omin = min(min(omin, min(o0, o1)), min(o2, o3));
+            omax = max(max(omax, max(o0, o1)), max(o2, o3));
         }
-        if (__any(cand)) {
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            omin = min(omin, (uint32_t)__shfl_xor((int)omin, o));
+            omax = max(omax, (uint32_t)__shfl_xor((int)omax, o));
+        }
+        const uint32_t range = omax - omin;
+        const int bits = range ? 32 - __builtin_clz(range) : 0;
+        const int shift = bits > 9 ? bits - 9 : 0;
+        uint32_t* h = bins[wave];
+#pragma unroll
+        for (int j = 0; j < NB / 64; ++j) h[lane * (NB / 64) + j] = 0u;
+#pragma unroll 4
+        for (int t = 0; t < SN / 256; ++t) {
+            const float4 v = *reinterpret_cast<const float4*>(rp + lo + t * 256 + lane * 4);
+            atomicAdd(&h[(float_order(score(v.x) + 0.f) - omin) >> shift], 1u);
+            atomicAdd(&h[(float_order(score(v.y) + 0.f) - omin) >> shift], 1u);
+            atomicAdd(&h[(float_order(score(v.z) + 0.f) - omin) >> shift], 1u);
+            atomicAdd(&h[(float_order(score(v.w) + 0.f) - omin) >> shift], 1u);
+        }
+        __builtin_amdgcn_s_waitcnt(waitcnt_lgkm0());
+        // rank of the guess among the SN prefix scores
+        const int64_t want = (3 * (int64_t)k * SN) / (2 * (hi - lo)) + 32;
+        constexpr int NBL = NB / 64;
+        int c[NBL], tot = 0;
+#pragma unroll
+        for (int j = 0; j < NBL; ++j) {
+            c[j] = (int)h[lane * NBL + j];
+            tot += c[j];
+            h[lane * NBL + j] = 0u;  // the pool expects zeroed bins
+        }
+        const int incl = wave_inclusive_sum(tot);
+        const uint64_t m = __ballot(incl - tot < want && want <= incl);
+        if (m) {
+            const int L = __builtin_ctzll(m);
+            int run = incl - tot, jb = NBL - 1;
+            bool f = false;
+#pragma unroll
+            for (int j = 0; j < NBL; ++j) {
+                run += c[j];
+                if (!f && run >= want) {
+                    jb = j;
+                    f = true;
+                }
+            }
+            const uint32_t b = (uint32_t)(L * NBL + __builtin_amdgcn_readlane(jb, L));
+            const uint64_t edge = (uint64_t)omin + (((uint64_t)b + 1) << shift) - 1;
+            guess = order_float(edge >= omax ? omax : (uint32_t)edge);
+        }
+    }
+
+    Pool pool;
+#pragma unroll 1
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        pool.init(k, pool_keys, 0, 1, nullptr, 1, bins[wave], drops);
+        int appended = 0;
+        auto offer = [&](float v, uint32_t i, bool ok) __attribute__((always_inline)) {
+            pool.refine_pools(false);  // room for the up to 64 keys one offer appends
+            const float sc[1] = {score(v)};
+            const int before = pool.cnt[0];
+            pool.offer(sc, i, ok && score(v) <= guess);
+            appended += pool.cnt[0] - before;
+        };
+        for (int64_t e = lo; e < vec_end; e += 256 * U) {
+            float4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                v[u] = *reinterpret_cast<const float4*>(rp + e + u * 256 + lane * 4);
+            const float th = fminf(guess, pool.kf[0]);
+            int c = 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                c += score(v[u].x) <= th;
+                c += score(v[u].y) <= th;
+                c += score(v[u].z) <= th;
+                c += score(v[u].w) <= th;
+            }
+            const int incl = wave_inclusive_sum(c);
+            const int total = __shfl(incl, 63);
+            if (total == 0) continue;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 stage[wave][4 * u + 0][lane] = v[u].x;
@@ -193,17 +278,42 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_pool(
                 stage[wave][4 * u + 3][lane] = v[u].w;
             }
             __builtin_amdgcn_wave_barrier();
+            // room first: a cut keeps at least k keys and tightens the
+            // threshold (the candidates counted above stay a superset)
+            if (pool.cnt[0] + total > Pool::CAP) pool.refine(0, k + 128);
+            if (pool.cnt[0] + total <= Pool::CAP) {
+                // bulk append: this lane's candidates at its prefix position
+                int pos = pool.cnt[0] + incl - c;
 #pragma unroll 1
-            for (int j = 0; j < 4 * U; ++j)
-                offer(stage[wave][j][lane], (uint32_t)(e + (j >> 2) * 256 + lane * 4 + (j & 3)),
-                      true);
+                for (int j = 0; c > 0; ++j) {
+                    const float x = stage[wave][j][lane];
+                    if (score(x) <= th) {
+                        const uint32_t i = (uint32_t)(e + (j >> 2) * 256 + lane * 4 + (j & 3));
+                        pool_keys[pos++] = make_key(score(x), i);
+                        --c;
+                    }
+                }
+                pool.cnt[0] += total;
+                appended += total;
+                // an offer (up to 64 keys) must find room: cut before it
+                pool.need_cut = pool.cnt[0] > Pool::CAP - 64;
+            } else {
+#pragma unroll 1
+                for (int j = 0; j < 4 * U; ++j)
+                    offer(stage[wave][j][lane], (uint32_t)(e + (j >> 2) * 256 + lane * 4 + (j & 3)),
+                          true);
+            }
             __builtin_amdgcn_wave_barrier();
         }
-    }
 #pragma unroll 1
-    for (int64_t e = vec_end; e < hi; e += 64) {
-        const int64_t i = e + lane;
-        offer(i < hi ? rp[i] : 0.f, (uint32_t)i, i < hi);
+        for (int64_t e = vec_end; e < hi; e += 64) {
+            const int64_t i = e + lane;
+            offer(i < hi ? rp[i] : 0.f, (uint32_t)i, i < hi);
+        }
+        // every score at or below the guess was appended (or beaten by k
+        // appended ones): with k of them the result is exact
+        if (appended >= k || guess == INFINITY) break;
+        guess = INFINITY;
     }
     pool.finish();  // at most 64 KR keys left, sentinel padded to that length
     // the pool's appends by every lane are visible to this wave's loads
