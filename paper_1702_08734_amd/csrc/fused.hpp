@@ -880,6 +880,13 @@ knn_fused(FusedArgs args) {
 
     constexpr int LPW = NI / kProducers;  // tile loads per producer wave
     static_assert(NI % kProducers == 0, "tile loads split evenly over the producers");
+    // Per-row side values of a tile (||y||^2 for L2, 1/scale for scaled
+    // formats) travel to LDS with it: producer wave r < NSIDE loads side
+    // array r for the tile's rows, one 4-byte load per lane, into a ring of
+    // NBUF + 1 slots, so the consumers' step loop issues no global load and
+    // never waits on the vector-memory counter, which on this chip also
+    // counts their own pool stores.
+    constexpr int NSIDE = (L2 ? 1 : 0) + (Op::SCALED ? 1 : 0);
     // Database tiles in flight: as many buffers as the LDS left after the
     // score slots and the smallest histograms holds (at most 6), loads
     // running NBUF - 1 steps ahead; the steps' barriers do not wait for
@@ -887,9 +894,10 @@ knn_fused(FusedArgs args) {
     // outstanding loads).
     constexpr int kLdsBytes = 160 * 1024;
     constexpr int TILE_BYTES = BN * GR * 16;
-    constexpr int OTHER = 2 * BN * LDQ * 4 + (S::mem_queues ? S::NC * 128 * 4 : 0) + 512;
+    constexpr int SIDE_BYTES = NSIDE * 7 * BN * 4;
+    constexpr int OTHER = 2 * BN * LDQ * 4 + SIDE_BYTES + (S::mem_queues ? S::NC * 128 * 4 : 0) + 512;
     constexpr int NB_LDS = (kLdsBytes - OTHER) / TILE_BYTES;
-    constexpr int NB_VM = 63 / LPW + 1;
+    constexpr int NB_VM = 63 / (LPW + (NSIDE > 0 ? 1 : 0)) + 1;
     constexpr int NB0 = NB_LDS < NB_VM ? NB_LDS : NB_VM;
     constexpr int NBUF = NB0 > 6 ? 6 : NB0 < 2 ? 2 : NB0;
     constexpr int AHEAD = NBUF - 1;
@@ -916,9 +924,10 @@ knn_fused(FusedArgs args) {
                         : (uint32_t)(uintptr_t)(lds_ptr_t)bt5;
     };
     __shared__ __align__(16) float scores[2][BN * LDQ];
+    __shared__ __align__(16) float side[NSIDE > 0 ? NSIDE : 1][NBUF + 1][BN];
     // histogram bins of each consumer's pool selections: as many as the LDS
     // left over allows (at most 1024)
-    constexpr int USED = NBUF * BN * GR * 16 + 2 * BN * LDQ * 4;
+    constexpr int USED = NBUF * BN * GR * 16 + 2 * BN * LDQ * 4 + SIDE_BYTES;
     constexpr int NBINS = !S::mem_queues                             ? 1
                           : USED + S::NC * 1024 * 4 <= kLdsBytes     ? 1024
                           : USED + S::NC * 512 * 4 <= kLdsBytes      ? 512
@@ -975,6 +984,28 @@ knn_fused(FusedArgs args) {
                      : "v"(src), "s"(m0)
                      : "memory", "m0");
     };
+    auto dma4 = [&](const float* src, uint32_t m0) __attribute__((always_inline)) {
+        asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off"
+                     :
+                     : "v"(src), "s"(m0)
+                     : "memory", "m0");
+    };
+    // side values of the tile at t0 into ring slot `slot` (producer waves
+    // below NSIDE; one more vector-memory operation for them per tile)
+    auto load_side = [&](int64_t t0, int slot) __attribute__((always_inline)) {
+        if constexpr (NSIDE > 0) {
+            if (wave < NSIDE) {
+                const float* src = (L2 && wave == 0) ? args.yn : args.yinv;
+                int64_t row = t0 + lane;
+                row = row < c1 ? row : c1 - 1;
+                if constexpr (VEC) {
+                    dma4(src + row, (uint32_t)(uintptr_t)(lds_ptr_t)&side[wave][slot][0]);
+                } else {
+                    side[wave][slot][lane] = src[row];
+                }
+            }
+        }
+    };
     auto load_tile = [&](int64_t t0, int buf) __attribute__((always_inline)) {
         const uint32_t base = tile_lds(buf) + (uint32_t)(wave * 64 * 16);
         if (t0 + BN <= c1) {  // wave-uniform: a whole tile of the chunk
@@ -1025,12 +1056,23 @@ knn_fused(FusedArgs args) {
         auto step_barrier = [&]() __attribute__((always_inline)) {
             asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
         };
+        // all but the newest AHEAD - 1 tiles' loads done (each producer
+        // wave: LPW loads per tile, one more when it loads a side array)
+        auto wait_ahead = [&]() __attribute__((always_inline)) {
+            if (NSIDE > 0 && wave < NSIDE)
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm<(AHEAD - 1) * (LPW + 1)>());
+            else
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm<(AHEAD - 1) * LPW>());
+        };
         // The first AHEAD tiles, then wait for tile 0 only.
 #pragma unroll
         for (int t = 0; t < AHEAD; ++t)
-            if (t < nsteps) load_tile(c0 + (int64_t)t * BN, t);
+            if (t < nsteps) {
+                load_tile(c0 + (int64_t)t * BN, t);
+                load_side(c0 + (int64_t)t * BN, t);
+            }
         if (nsteps >= AHEAD)
-            __builtin_amdgcn_s_waitcnt(waitcnt_vm<(AHEAD - 1) * LPW>());
+            wait_ahead();
         else
             __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -1071,7 +1113,10 @@ knn_fused(FusedArgs args) {
                         acc[s4 % SK][qb][db] = Op::mma(acc[s4 % SK][qb][db], areg[qb][s4], b[s4][db]);
             __builtin_amdgcn_sched_barrier(0);
             const bool issue = s + AHEAD < nsteps;
-            if (issue) load_tile(c0 + (int64_t)(s + AHEAD) * BN, (u + AHEAD) % NBUF);
+            if (issue) {
+                load_tile(c0 + (int64_t)(s + AHEAD) * BN, (u + AHEAD) % NBUF);
+                load_side(c0 + (int64_t)(s + AHEAD) * BN, (s + AHEAD) % (NBUF + 1));
+            }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int s4 = H; s4 < S4; ++s4)
@@ -1097,7 +1142,7 @@ knn_fused(FusedArgs args) {
             // the barrier covers the other producers); the AHEAD - 1 tiles
             // after it stay in flight
             if (issue)
-                __builtin_amdgcn_s_waitcnt(waitcnt_vm<(AHEAD - 1) * LPW>());
+                wait_ahead();
             else
                 __builtin_amdgcn_s_waitcnt(0);
         };
@@ -1143,11 +1188,6 @@ knn_fused(FusedArgs args) {
             qs[qq] = (Op::SCALED && q < args.nq) ? args.qinv[q] : 1.f;
         }
         __syncthreads();
-        float ynext = 0.f, ysnext = 1.f;
-        if (c0 + lane < c1) {
-            if (L2) ynext = args.yn[c0 + lane];
-            if (Op::SCALED) ysnext = args.yinv[c0 + lane];
-        }
         // bound exchanges: often early, while the queues fill (steps 0, 4, 8,
         // 16, 32), then every 64 steps
         int next_x = args.bound ? 0 : nsteps + 1;
@@ -1174,11 +1214,11 @@ knn_fused(FusedArgs args) {
                 const float* slot = scores[(s - 1) & 1];
                 const int64_t g = c0 + (int64_t)(s - 1) * BN + lane;
                 const bool ok = g < c1;
-                const float ynv = ynext, ysv = ysnext;
-                if (g + BN < c1) {
-                    if (L2) ynext = args.yn[g + BN];
-                    if (Op::SCALED) ysnext = args.yinv[g + BN];
-                }
+                // side values of step s - 1's tile (landed before the barrier
+                // that ended step s - 2; overwritten only after this step)
+                const int ring = (s - 1) % (NBUF + 1);
+                const float ynv = L2 ? side[0][ring][lane] : 0.f;
+                const float ysv = Op::SCALED ? side[L2 ? 1 : 0][ring][lane] : 1.f;
                 float score[QW];
                 const float* col = slot + lane * LDQ + cw * QW;
                 if constexpr (QW % 4 == 0) {

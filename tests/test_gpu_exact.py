@@ -86,6 +86,29 @@ def test_kselect_benchmark_shape_sampled(api, k):
     np.testing.assert_array_equal(v.cpu().numpy()[rows].astype(np.float64), vo)
 
 
+@pytest.mark.parametrize("largest", [False, True])
+@pytest.mark.parametrize("k", [300, 1000])
+def test_kselect_threshold_guess_rows(api, k, largest):
+    # 8,200 rows of 33,000 values: one segment per row, long enough for the
+    # sampled threshold guess.  Rows 0-63 ascending (the guess, taken from
+    # the row's start, is far too low: the plain second pass must run), rows
+    # 64-127 descending (far too high), rows 128-191 small-integer ties,
+    # the rest U[0,1).
+    say(f"kselect guess rows k={k} largest={largest}")
+    rng = np.random.default_rng(1000 + k + int(largest))
+    a = rng.random((8200, 33_000), dtype=np.float32)
+    a[0:64] = np.sort(a[0:64], axis=1)
+    a[64:128] = np.sort(a[64:128], axis=1)[:, ::-1]
+    a[128:192] = rng.integers(0, 40, size=(64, 33_000)).astype(np.float32)
+    v, i = api.kselect(dev(a), k, largest)
+    torch.cuda.synchronize()
+    rows = np.concatenate([np.arange(0, 8), np.arange(60, 70), np.arange(124, 134),
+                           np.arange(186, 196), np.arange(200, 8200, 397)])
+    vo, io = oracle.kselect(np.ascontiguousarray(a[rows]), k, largest)
+    np.testing.assert_array_equal(i.cpu().numpy()[rows], io)
+    np.testing.assert_array_equal(v.cpu().numpy()[rows].astype(np.float64), vo)
+
+
 # ------------------------------------------------------------ exact k-NN
 def test_knn_exact_small_full(api):
     # 50,000 x 64 N(0,1), 500 queries, k = 10: every query against the oracle
