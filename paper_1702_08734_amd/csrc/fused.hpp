@@ -956,15 +956,19 @@ knn_fused(FusedArgs args) {
     // tile are fixed (loff).  Rows past the chunk repeat its last row and
     // granules past the valid elements repeat granule 0: both only ever meet
     // zero A components or unconsumed score columns.
-    int32_t loff[LPW], lrow[LPW], lcc[LPW];
+    // (row j inside the tile, granule cc of the row) of load t of this lane;
+    // only the fast path keeps its offsets, the others recompute them
+    auto granule_of = [&](int t, int& j, int& cc) __attribute__((always_inline)) {
+        const int g = (wave + t * kProducers) * 64 + lane;
+        j = g / GR;
+        const int c = (g % GR) ^ (j & SW);
+        cc = c * Op::EPG < args.valid ? c : 0;
+    };
+    int32_t loff[LPW];
 #pragma unroll
     for (int t = 0; t < LPW; ++t) {
-        const int g = (wave + t * kProducers) * 64 + lane;
-        const int j = g / GR;
-        const int c = (g % GR) ^ (j & SW);
-        const int cc = c * Op::EPG < args.valid ? c : 0;
-        lrow[t] = j;
-        lcc[t] = cc;
+        int j, cc;
+        granule_of(t, j, cc);
         loff[t] = (int32_t)(j * row_bytes + cc * 16);
     }
     // Direct global-to-LDS load of 16 bytes per lane (lane i writes at LDS
@@ -1014,20 +1018,24 @@ knn_fused(FusedArgs args) {
                 if constexpr (VEC) {
                     dma16(xb + t0 * row_bytes + loff[t], base + (uint32_t)(t * kProducers * 64 * 16));
                 } else {
+                    int j, cc;
+                    granule_of(t, j, cc);
                     tile_buf(buf)[(wave + t * kProducers) * 64 + lane] =
-                        load_granule<Op, false>(xb + (t0 + lrow[t]) * row_bytes, lcc[t], args.valid, true);
+                        load_granule<Op, false>(xb + (t0 + j) * row_bytes, cc, args.valid, true);
                 }
             }
         } else {
 #pragma unroll
             for (int t = 0; t < LPW; ++t) {
-                int64_t row = t0 + lrow[t];
+                int j, cc;
+                granule_of(t, j, cc);
+                int64_t row = t0 + j;
                 row = row < c1 ? row : c1 - 1;
                 if constexpr (VEC) {
-                    dma16(xb + row * row_bytes + lcc[t] * 16, base + (uint32_t)(t * kProducers * 64 * 16));
+                    dma16(xb + row * row_bytes + cc * 16, base + (uint32_t)(t * kProducers * 64 * 16));
                 } else {
                     tile_buf(buf)[(wave + t * kProducers) * 64 + lane] =
-                        load_granule<Op, false>(xb + row * row_bytes, lcc[t], args.valid, true);
+                        load_granule<Op, false>(xb + row * row_bytes, cc, args.valid, true);
                 }
             }
         }
