@@ -1377,47 +1377,71 @@ __global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
 
     // FP32 direct-form distances of the first keff keys: 16 lanes per row and
     // 4 rows per pass, each lane summing every 16th 16-byte granule of the
-    // row (coalesced), then a 16-lane reduction
+    // row (coalesced), then a 16-lane reduction.  Four passes (16 rows) go
+    // together so that their row loads are in flight at once (the gathers
+    // are latency-bound one pass at a time).
+    constexpr int NP = 4;
     const int sub = lane & 15, rsel = lane >> 4;
     const float* xw = xs[wave];
 #pragma unroll 1
-    for (int e0 = 0; e0 < keff; e0 += 4) {
-        const int e = e0 + rsel;
-        const uint64_t key = e < keff ? kl[wave][e] : kSentinel;
-        float sacc = 0.f;
-        if (key != kSentinel) {
-            const float* y = xb + (int64_t)key_index(key) * d;
-            if (vec) {
-                for (int t = 4 * sub; t < d; t += 64) {
-                    const float4 yv = *reinterpret_cast<const float4*>(y + t);
-                    const float4 xv = *reinterpret_cast<const float4*>(xw + t);
+    for (int e0 = 0; e0 < keff; e0 += 4 * NP) {
+        const float* y[NP];
+        bool live[NP];
+        float sacc[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int e = e0 + 4 * p + rsel;
+            const uint64_t key = e < keff ? kl[wave][e] : kSentinel;
+            live[p] = key != kSentinel;
+            y[p] = xb + (int64_t)(live[p] ? key_index(key) : 0u) * d;
+            sacc[p] = 0.f;
+        }
+        if (vec) {
+            for (int t = 4 * sub; t < d; t += 64) {
+                float4 yv[NP];
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    yv[p] = live[p] ? *reinterpret_cast<const float4*>(y[p] + t) : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float4 xv = *reinterpret_cast<const float4*>(xw + t);
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
                     if (l2) {
-                        const float a = xv.x - yv.x, b = xv.y - yv.y, c = xv.z - yv.z, dd = xv.w - yv.w;
-                        sacc = fmaf(a, a, sacc);
-                        sacc = fmaf(b, b, sacc);
-                        sacc = fmaf(c, c, sacc);
-                        sacc = fmaf(dd, dd, sacc);
+                        const float a = xv.x - yv[p].x, b = xv.y - yv[p].y, c = xv.z - yv[p].z,
+                                    dd = xv.w - yv[p].w;
+                        sacc[p] = fmaf(a, a, sacc[p]);
+                        sacc[p] = fmaf(b, b, sacc[p]);
+                        sacc[p] = fmaf(c, c, sacc[p]);
+                        sacc[p] = fmaf(dd, dd, sacc[p]);
                     } else {
-                        sacc = fmaf(xv.x, yv.x, sacc);
-                        sacc = fmaf(xv.y, yv.y, sacc);
-                        sacc = fmaf(xv.z, yv.z, sacc);
-                        sacc = fmaf(xv.w, yv.w, sacc);
+                        sacc[p] = fmaf(xv.x, yv[p].x, sacc[p]);
+                        sacc[p] = fmaf(xv.y, yv[p].y, sacc[p]);
+                        sacc[p] = fmaf(xv.z, yv[p].z, sacc[p]);
+                        sacc[p] = fmaf(xv.w, yv[p].w, sacc[p]);
                     }
                 }
-            } else {
-                for (int t = sub; t < d; t += 16) {
+            }
+        } else {
+            for (int t = sub; t < d; t += 16) {
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    const float yt = live[p] ? y[p][t] : 0.f;
                     if (l2) {
-                        const float a = xw[t] - y[t];
-                        sacc = fmaf(a, a, sacc);
+                        const float a = xw[t] - yt;
+                        sacc[p] = fmaf(a, a, sacc[p]);
                     } else {
-                        sacc = fmaf(xw[t], y[t], sacc);
+                        sacc[p] = fmaf(xw[t], yt, sacc[p]);
                     }
                 }
             }
         }
 #pragma unroll
-        for (int o = 8; o >= 1; o >>= 1) sacc += __shfl_xor(sacc, o, 16);
-        if (sub == 0 && e < keff) dist[wave][e] = sacc;
+        for (int p = 0; p < NP; ++p) {
+            float v = live[p] ? sacc[p] : 0.f;
+#pragma unroll
+            for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 16);
+            const int e = e0 + 4 * p + rsel;
+            if (sub == 0 && e < keff) dist[wave][e] = v;
+        }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
