@@ -217,13 +217,18 @@ __device__ __forceinline__ uint64_t wave_max64(uint64_t v) {
     v = umax64(v, xor_lane64<16>(v));
     return umax64(v, xor_lane64<32>(v));
 }
+// Inclusive prefix sum over the wave's 64 lanes with DPP moves (no LDS
+// round trip): shifts by 1, 2, 4 and 8 lanes inside each 16-lane row, then
+// lane 15 of rows 0 and 2 added to rows 1 and 3 and lane 31 to rows 2 and 3.
+// A lane whose source lies outside its row, or whose row is masked off,
+// adds 0.
 __device__ __forceinline__ int wave_inclusive_sum(int v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int u = __shfl_up(v, o);
-        v += lane >= o ? u : 0;
-    }
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
     return v;
 }
 
