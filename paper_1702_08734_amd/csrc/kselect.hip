@@ -268,7 +268,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void kselect_pool(
                 c += score(v[u].w) <= th;
             }
             const int incl = wave_inclusive_sum(c);
-            const int total = __shfl(incl, 63);
+            const int total = __builtin_amdgcn_readlane(incl, 63);
             if (total == 0) continue;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
