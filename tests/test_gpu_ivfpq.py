@@ -388,12 +388,20 @@ def test_ivfpq_rerank_matches_oracle(api, small_index, k, nprobe, R):
     coarse, books = ix.get_quantizers()
     offs, codes, ids = ix.get_lists()
     rows = np.arange(0, 300, 5)
+    fails, skipped = check_rerank(D.cpu().numpy()[rows], I.cpu().numpy()[rows], xq, xb, rows,
+                                  coarse, books, offs, codes, ids, k, nprobe, R)
+    assert not fails, fails[:10]
+    assert skipped <= 3
+
+
+def check_rerank(Dg, Ig, xq, xb, rows, coarse, books, offs, codes, ids, k, nprobe, R):
+    """Band rule for re-ranked IVFADC results against the oracle; returns
+    (failures, rows skipped as band-ambiguous)."""
     # short lists whose R-th ADC value is band-ambiguous may legitimately
     # differ; the oracle's R + 1 values tell which rows those are
     Da, Ia = oracle.ivfpq_search(xq[rows], coarse, books, offs, codes, ids, R + 1, nprobe)
     Do, Io = oracle.ivfpq_search_rerank(xq[rows], coarse, books, offs, codes, ids, xb, k,
                                         nprobe, R)
-    Dg, Ig = D.cpu().numpy()[rows], I.cpu().numpy()[rows]
     skipped, fails = 0, []
     for j, q in enumerate(rows):
         x = xq[q].astype(np.float64)
@@ -426,8 +434,7 @@ def test_ivfpq_rerank_matches_oracle(api, small_index, k, nprobe, R):
             if lo and hi and gi[r] != oi[r]:
                 fails.append(f"q{q}: rank {r} id {gi[r]} != oracle {oi[r]}")
                 break
-    assert not fails, fails[:10]
-    assert skipped <= 3
+    return fails, skipped
 
 
 def test_ivfpq_rerank_errors(api, small_index):
