@@ -14,6 +14,8 @@ namespace mk {
 
 void set_error(const std::string& msg);
 const char* get_error();
+// Once per device: the default memory pool keeps freed scratch memory.
+void keep_pool_memory();
 
 #define MK_REQUIRE(cond, status, msg)                      \
     do {                                                   \
@@ -94,6 +96,7 @@ struct Scratch {
             owned = false;
             return MK_OK;
         }
+        keep_pool_memory();
         hipError_t e = hipMallocAsync(&ptr, bytes, s);
         if (e != hipSuccess) {
             ptr = nullptr;
