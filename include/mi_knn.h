@@ -513,7 +513,9 @@ mk_status mk_ivfpq_shape(const mk_ivfpq* index, int32_t* d, int32_t* nlist, int3
 /*
  * Upper bound on the device workspace (bytes) that one search of nq queries
  * allocates: mk_ivfpq_search (R = 0), mk_ivfpq_search_rerank (R > 0) or
- * mk_ivfpq_search_learned (nprobe = cap).  Used for admission control.
+ * mk_ivfpq_search_learned (nprobe = cap; not counting the network's hidden
+ * activations, two rows of its hidden width per query).  Used for admission
+ * control and to size the serving loop's workspaces.
  */
 mk_status mk_ivfpq_search_workspace_bytes(const mk_ivfpq* index, int64_t nq, int32_t k,
                                           int32_t nprobe, int32_t R, size_t* bytes);
@@ -525,6 +527,10 @@ mk_status mk_ivfpq_search_workspace_bytes(const mk_ivfpq* index, int64_t nq, int
  * bytes (the first request of a batch is always admitted); nstreams
  * batches are in flight at once, each on its own HIP stream with pinned
  * staging buffers, so transfers and kernels of consecutive batches overlap.
+ * Each stream also holds a device workspace of
+ * mk_ivfpq_search_workspace_bytes for max_batch rows plus a quarter and
+ * 64 MiB, allocated at creation, from which its batches' scratch is carved
+ * (scratch that does not fit is allocated per search as usual).
  * A request's results equal those of searching it alone.
  * ------------------------------------------------------------------------ */
 

@@ -1,5 +1,6 @@
-// Library-wide C ABI helpers: version, the per-thread error message, and
-// the setting of the stream-ordered allocator's pool.
+// Library-wide C ABI helpers: version, the per-thread error message, the
+// setting of the stream-ordered allocator's pool and the per-thread default
+// scratch arena.
 #include <mutex>
 #include <vector>
 
@@ -34,6 +35,14 @@ void keep_pool_memory() {
     uint64_t threshold = ~0ull;
     (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
 }
+
+static thread_local Arena* g_thread_arena = nullptr;
+
+Arena* thread_arena() { return g_thread_arena; }
+
+ArenaScope::ArenaScope(Arena* a) : prev_(g_thread_arena) { g_thread_arena = a; }
+
+ArenaScope::~ArenaScope() { g_thread_arena = prev_; }
 
 }  // namespace mk
 

@@ -64,9 +64,28 @@ struct Arena {
 
 inline bool sizing_only(const Arena* a) { return a && a->sizing; }
 
+// The calling thread's default arena: scratch requested without an explicit
+// arena is carved from it while an ArenaScope is alive on that thread, and
+// taken from the stream-ordered allocator when it does not fit (or when no
+// scope is active).  A long-lived caller that launches one call at a time per
+// stream (the serving loop: one workspace per stream) thereby makes no
+// allocator calls per search.
+Arena* thread_arena();
+class ArenaScope {
+public:
+    explicit ArenaScope(Arena* a);
+    ~ArenaScope();
+    ArenaScope(const ArenaScope&) = delete;
+    ArenaScope& operator=(const ArenaScope&) = delete;
+
+private:
+    Arena* prev_;
+};
+
 // Device scratch: stream-ordered allocations freed on the same stream when
 // they go out of scope (so a call never synchronises to release them), or,
-// with an arena, a slice of the arena that is never freed.
+// with an arena (explicit, else the thread's), a slice of the arena that is
+// never freed.
 struct Scratch {
     void* ptr = nullptr;
     hipStream_t stream = nullptr;
@@ -95,6 +114,15 @@ struct Scratch {
             arena->used = start + bytes;
             owned = false;
             return MK_OK;
+        }
+        if (Arena* t = thread_arena()) {
+            const size_t start = (t->used + 255) & ~(size_t)255;
+            if (start <= t->size && bytes <= t->size - start) {
+                ptr = t->base + start;
+                t->used = start + bytes;
+                owned = false;
+                return MK_OK;
+            }
         }
         keep_pool_memory();
         hipError_t e = hipMallocAsync(&ptr, bytes, s);

@@ -3,7 +3,10 @@
 // row limit and a device-memory budget for the search workspace, and each
 // batch runs on one of several HIP streams (pinned staging, upload, search,
 // download), so that one batch's transfers and kernels overlap the next
-// batch's.  A completion thread copies each request's rows back to the
+// batch's.  Each stream has its own search workspace, so a batch makes no
+// allocator calls (per-search allocations through the stream-ordered
+// allocator cost the launching thread more than the GPU time of a small
+// batch).  A completion thread copies each request's rows back to the
 // caller's buffers and records its latency (submission to completion).
 //
 // Every query's result is independent of the batch it shares: the search
@@ -50,6 +53,8 @@ struct Slot {
     float* d_q = nullptr;
     float* d_D = nullptr;
     int64_t* d_I = nullptr;
+    unsigned char* d_ws = nullptr;  // the search scratch of this slot's batches
+    size_t ws_bytes = 0;
     std::vector<std::shared_ptr<Request>> reqs;
     int64_t rows = 0;
     mk_status status = MK_OK;
@@ -95,6 +100,13 @@ void launch_batch(mk_server* sv, Slot& sl) {
     if (e != hipSuccess) sl.status = MK_ERR_DEVICE;
     if (sl.status == MK_OK) {
         const mk_server_config& c = sv->cfg;
+        // the search's scratch is carved from the slot's workspace, which the
+        // slot's previous batch no longer uses (it has completed before the
+        // slot was handed out again)
+        mk::Arena arena;
+        arena.base = sl.d_ws;
+        arena.size = sl.ws_bytes;
+        mk::ArenaScope scope(&arena);
         if (c.net)
             sl.status = mk_ivfpq_search_learned(sv->ix, c.net, c.delta, sl.d_q, off, k, c.cap, c.R,
                                                 c.xb, c.nb, sl.d_D, sl.d_I, nullptr, sl.stream);
@@ -211,7 +223,7 @@ void release(mk_server* sv) {
         if (sl.ready) (void)hipEventDestroy(sl.ready);
         for (void* p : {(void*)sl.h_q, (void*)sl.h_D, (void*)sl.h_I})
             if (p) (void)hipHostFree(p);
-        for (void* p : {(void*)sl.d_q, (void*)sl.d_D, (void*)sl.d_I})
+        for (void* p : {(void*)sl.d_q, (void*)sl.d_D, (void*)sl.d_I, (void*)sl.d_ws})
             if (p) (void)hipFree(p);
     }
     sv->slots.clear();
@@ -229,6 +241,8 @@ extern "C" mk_status mk_server_create(mk_ivfpq* ix, const mk_server_config* cfg,
     MK_REQUIRE(cfg->k >= 1 && cfg->max_batch >= 1 && cfg->nstreams >= 1 && cfg->nstreams <= 8,
                MK_ERR_INVALID_ARG, "need k >= 1, max_batch >= 1, 1 <= nstreams <= 8");
     MK_REQUIRE(cfg->net || cfg->nprobe >= 1, MK_ERR_INVALID_ARG, "need nprobe >= 1");
+    MK_REQUIRE(!cfg->net || cfg->cap >= 1, MK_ERR_INVALID_ARG,
+               "a learned probe count needs cap >= 1");
     MK_REQUIRE(cfg->R <= 0 || (cfg->xb && cfg->R >= cfg->k), MK_ERR_INVALID_ARG,
                "a re-rank needs xb and R >= k");
     const int32_t d = mk_ivfpq_dim(ix);
@@ -239,6 +253,16 @@ extern "C" mk_status mk_server_create(mk_ivfpq* ix, const mk_server_config* cfg,
     MK_HIP(hipGetDevice(&sv->device));
     sv->slots.resize(cfg->nstreams);
     const size_t B = (size_t)cfg->max_batch;
+    // per-slot search workspace: the estimate for a full batch plus a margin
+    // for what it leaves out (scratch that does not fit is allocated as usual)
+    size_t ws = 0;
+    {
+        mk_status st = mk_ivfpq_search_workspace_bytes(ix, cfg->max_batch, cfg->k,
+                                                       cfg->net ? cfg->cap : cfg->nprobe, cfg->R,
+                                                       &ws);
+        if (st != MK_OK) return st;
+    }
+    ws += ws / 4 + ((size_t)64 << 20);
     hipError_t e = hipSuccess;
     for (Slot& sl : sv->slots) {
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
@@ -249,6 +273,8 @@ extern "C" mk_status mk_server_create(mk_ivfpq* ix, const mk_server_config* cfg,
         if (e == hipSuccess) e = hipMalloc(&sl.d_q, sizeof(float) * B * d);
         if (e == hipSuccess) e = hipMalloc(&sl.d_D, sizeof(float) * B * cfg->k);
         if (e == hipSuccess) e = hipMalloc(&sl.d_I, sizeof(int64_t) * B * cfg->k);
+        if (e == hipSuccess) e = hipMalloc(&sl.d_ws, ws);
+        if (e == hipSuccess) sl.ws_bytes = ws;
     }
     if (e != hipSuccess) {
         mk::release(sv.get());
