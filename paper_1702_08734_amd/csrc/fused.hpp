@@ -1307,16 +1307,23 @@ inline mk_status clear_bounds(int KR, uint32_t* bound, int64_t nq, int64_t nchun
 // each fill their queue before shared bounds can help, and a pool's
 // insertions grow with the number of chunks, so long queues get few, long
 // chunks: about 2 workgroups per CU for queues of 512+ entries, 16
-// otherwise, chunks of at least 32 queue lengths, at most kMaxRankChunks
-// chunks, and among chunk counts within 25% of that target the one whose
-// last wave of workgroups is fullest.
+// otherwise, chunks of at least 32 queue lengths (8 for short queues when
+// that would leave most CUs idle), at most kMaxRankChunks chunks, and among
+// chunk counts within 25% of that target the one whose last wave of
+// workgroups is fullest.
 inline void plan_chunks(int64_t nq, int64_t nb, int BQ, int BN, int KS, int64_t* nqb,
                         int64_t* nchunks, int64_t* chunk_len) {
     constexpr int64_t kCUs = 256;
     *nqb = ceil_div(nq, BQ);
     const int64_t target = (KS >= 512 ? 2 : 16) * kCUs;
     const int64_t want = ceil_div(target, *nqb);
-    int64_t max_by_len = nb / (32 * KS) > 1 ? nb / (32 * KS) : 1;
+    // short queues (128 entries or fewer) over a database that gives fewer
+    // than kCUs / 2 workgroups at 32 queue lengths per chunk (a small batch
+    // against IVF coarse centroids): chunks of 8 queue lengths, since then
+    // the sweep's step count, not the insertions, sets the time
+    const int64_t min_len =
+        (KS <= 128 && *nqb * (nb / (32 * KS)) < kCUs / 2) ? 8 * (int64_t)KS : 32 * (int64_t)KS;
+    int64_t max_by_len = nb / min_len > 1 ? nb / min_len : 1;
     if (max_by_len > kMaxRankChunks) max_by_len = kMaxRankChunks;
     int64_t hi = want < max_by_len ? want : max_by_len;
     if (hi < 1) hi = 1;
@@ -1339,6 +1346,102 @@ inline void plan_chunks(int64_t nq, int64_t nb, int BQ, int BN, int KS, int64_t*
 
 constexpr int kMergeWaves = 4;
 constexpr int kMaxDim = 512;
+
+// FP32 direct-form squared distances (l2) or inner products of the query row
+// xw (in LDS) to the database rows named by one wave's keys kl[e], e in
+// [e0, e0 + 16), written to dist[e] for e < keff (sentinel keys: 0).  16
+// lanes per row and 4 rows per pass, each lane summing every 16th 16-byte
+// granule of the row (coalesced), then a 16-lane reduction; the four passes'
+// row loads are in flight together (the gathers are latency-bound one pass
+// at a time).
+__device__ __forceinline__ void rerank_rows16(const float* xw, const uint64_t* kl, int e0,
+                                              int keff, const float* __restrict__ xb, int32_t d,
+                                              int32_t vec, int32_t l2, float* dist) {
+    constexpr int NP = 4;
+    const int lane = lane_id();
+    const int sub = lane & 15, rsel = lane >> 4;
+    const float* y[NP];
+    bool live[NP];
+    float sacc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int e = e0 + 4 * p + rsel;
+        const uint64_t key = e < keff ? kl[e] : kSentinel;
+        live[p] = key != kSentinel;
+        y[p] = xb + (int64_t)(live[p] ? key_index(key) : 0u) * d;
+        sacc[p] = 0.f;
+    }
+    if (vec) {
+        for (int t = 4 * sub; t < d; t += 64) {
+            float4 yv[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                yv[p] = live[p] ? *reinterpret_cast<const float4*>(y[p] + t) : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 xv = *reinterpret_cast<const float4*>(xw + t);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                if (l2) {
+                    const float a = xv.x - yv[p].x, b = xv.y - yv[p].y, c = xv.z - yv[p].z,
+                                dd = xv.w - yv[p].w;
+                    sacc[p] = fmaf(a, a, sacc[p]);
+                    sacc[p] = fmaf(b, b, sacc[p]);
+                    sacc[p] = fmaf(c, c, sacc[p]);
+                    sacc[p] = fmaf(dd, dd, sacc[p]);
+                } else {
+                    sacc[p] = fmaf(xv.x, yv[p].x, sacc[p]);
+                    sacc[p] = fmaf(xv.y, yv[p].y, sacc[p]);
+                    sacc[p] = fmaf(xv.z, yv[p].z, sacc[p]);
+                    sacc[p] = fmaf(xv.w, yv[p].w, sacc[p]);
+                }
+            }
+        }
+    } else {
+        for (int t = sub; t < d; t += 16) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const float yt = live[p] ? y[p][t] : 0.f;
+                if (l2) {
+                    const float a = xw[t] - yt;
+                    sacc[p] = fmaf(a, a, sacc[p]);
+                } else {
+                    sacc[p] = fmaf(xw[t], yt, sacc[p]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        float v = live[p] ? sacc[p] : 0.f;
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 16);
+        const int e = e0 + 4 * p + rsel;
+        if (sub == 0 && e < keff) dist[e] = v;
+    }
+}
+
+
+// The first k of a wave's sorted (score, row) keys as distances (L2) or
+// inner products and row ids; sentinels become (+-inf, -1).
+template <int KR>
+__device__ __forceinline__ void emit_reranked(const uint64_t (&nk)[KR], int32_t k, int32_t l2,
+                                              float* __restrict__ Dq, int64_t* __restrict__ Iq) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const int e = r * 64 + lane;
+        if (e < k) {
+            const uint64_t key = nk[r];
+            if (key == kSentinel) {
+                Dq[e] = l2 ? INFINITY : -INFINITY;
+                Iq[e] = -1;
+            } else {
+                const float s = key_score(key);
+                Dq[e] = l2 ? s : -s;
+                Iq[e] = (int64_t)key_index(key);
+            }
+        }
+    }
+}
 
 template <int KR>
 __global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
@@ -1380,74 +1483,11 @@ __global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
 
-    // FP32 direct-form distances of the first keff keys: 16 lanes per row and
-    // 4 rows per pass, each lane summing every 16th 16-byte granule of the
-    // row (coalesced), then a 16-lane reduction.  Four passes (16 rows) go
-    // together so that their row loads are in flight at once (the gathers
-    // are latency-bound one pass at a time).
-    constexpr int NP = 4;
-    const int sub = lane & 15, rsel = lane >> 4;
+    // exact distances of the first keff keys, 16 rows per step
     const float* xw = xs[wave];
 #pragma unroll 1
-    for (int e0 = 0; e0 < keff; e0 += 4 * NP) {
-        const float* y[NP];
-        bool live[NP];
-        float sacc[NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const int e = e0 + 4 * p + rsel;
-            const uint64_t key = e < keff ? kl[wave][e] : kSentinel;
-            live[p] = key != kSentinel;
-            y[p] = xb + (int64_t)(live[p] ? key_index(key) : 0u) * d;
-            sacc[p] = 0.f;
-        }
-        if (vec) {
-            for (int t = 4 * sub; t < d; t += 64) {
-                float4 yv[NP];
-#pragma unroll
-                for (int p = 0; p < NP; ++p)
-                    yv[p] = live[p] ? *reinterpret_cast<const float4*>(y[p] + t) : make_float4(0.f, 0.f, 0.f, 0.f);
-                const float4 xv = *reinterpret_cast<const float4*>(xw + t);
-#pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    if (l2) {
-                        const float a = xv.x - yv[p].x, b = xv.y - yv[p].y, c = xv.z - yv[p].z,
-                                    dd = xv.w - yv[p].w;
-                        sacc[p] = fmaf(a, a, sacc[p]);
-                        sacc[p] = fmaf(b, b, sacc[p]);
-                        sacc[p] = fmaf(c, c, sacc[p]);
-                        sacc[p] = fmaf(dd, dd, sacc[p]);
-                    } else {
-                        sacc[p] = fmaf(xv.x, yv[p].x, sacc[p]);
-                        sacc[p] = fmaf(xv.y, yv[p].y, sacc[p]);
-                        sacc[p] = fmaf(xv.z, yv[p].z, sacc[p]);
-                        sacc[p] = fmaf(xv.w, yv[p].w, sacc[p]);
-                    }
-                }
-            }
-        } else {
-            for (int t = sub; t < d; t += 16) {
-#pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    const float yt = live[p] ? y[p][t] : 0.f;
-                    if (l2) {
-                        const float a = xw[t] - yt;
-                        sacc[p] = fmaf(a, a, sacc[p]);
-                    } else {
-                        sacc[p] = fmaf(xw[t], yt, sacc[p]);
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            float v = live[p] ? sacc[p] : 0.f;
-#pragma unroll
-            for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 16);
-            const int e = e0 + 4 * p + rsel;
-            if (sub == 0 && e < keff) dist[wave][e] = v;
-        }
-    }
+    for (int e0 = 0; e0 < keff; e0 += 16)
+        rerank_rows16(xw, kl[wave], e0, keff, xb, d, vec, l2, dist[wave]);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
 
@@ -1463,21 +1503,50 @@ __global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
         }
     }
     bitonic_sort<false, KR>(nk);
+    emit_reranked<KR>(nk, k, l2, D + q * k, I + q * k);
+}
+
+// Exact re-rank of one query's short list (the first R keys of its row of
+// 64 * KR) by a whole workgroup: the waves share the rows' exact distances,
+// 16 rows per wave per step, then wave 0 sorts the (distance, row) keys and
+// writes the first k.  The same rows, distances and final sort as
+// knn_merge_rerank over one chunk of R, so the same results, with a quarter
+// of its gather latency per query: for batches too small to fill the chip
+// with one wave per query.
+template <int KR>
+__global__ __launch_bounds__(64 * kMergeWaves) void knn_rerank_block(
+    const uint64_t* __restrict__ keys, int32_t R, const float* __restrict__ xq,
+    const float* __restrict__ xb, int32_t d, int32_t vec, int32_t l2, int32_t k,
+    float* __restrict__ D, int64_t* __restrict__ I) {
+    constexpr int KS = 64 * KR;
+    __shared__ __align__(16) float xs[kMaxDim];
+    __shared__ uint64_t kl[KS];
+    __shared__ float dist[KS];
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int64_t q = blockIdx.x;
+    const uint64_t* p = keys + q * KS;
+    for (int e = threadIdx.x; e < KS; e += 64 * kMergeWaves) kl[e] = e < R ? p[e] : kSentinel;
+    for (int t = threadIdx.x; t < d; t += 64 * kMergeWaves) xs[t] = xq[q * d + t];
+    __syncthreads();
+#pragma unroll 1
+    for (int e0 = 16 * wave; e0 < R; e0 += 16 * kMergeWaves)
+        rerank_rows16(xs, kl, e0, R, xb, d, vec, l2, dist);
+    __syncthreads();
+    if (wave != 0) return;
+    uint64_t nk[KR];
 #pragma unroll
     for (int r = 0; r < KR; ++r) {
         const int e = r * 64 + lane;
-        if (e < k) {
-            const uint64_t key = nk[r];
-            if (key == kSentinel) {
-                D[q * k + e] = l2 ? INFINITY : -INFINITY;
-                I[q * k + e] = -1;
-            } else {
-                const float s = key_score(key);
-                D[q * k + e] = l2 ? s : -s;
-                I[q * k + e] = (int64_t)key_index(key);
-            }
+        const uint64_t key = kl[e];
+        nk[r] = kSentinel;
+        if (key != kSentinel && e < R) {
+            const float sv = dist[e];
+            nk[r] = make_key(l2 ? sv : -sv, key_index(key));
         }
     }
+    bitonic_sort<false, KR>(nk);
+    emit_reranked<KR>(nk, k, l2, D + q * k, I + q * k);
 }
 
 

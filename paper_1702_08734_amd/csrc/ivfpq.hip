@@ -1336,9 +1336,10 @@ extern "C" mk_status mk_ivfpq_search_workspace_bytes(const mk_ivfpq* ix, int64_t
     MK_REQUIRE(nq >= 0 && k >= 1 && nprobe >= 1, MK_ERR_INVALID_ARG, "bad sizes");
     const int64_t kk = R > 0 ? R : k;
     const int64_t qn = nq;
-    // coarse search: results, and at most nlist / (32 * queue) chunk lists
+    // coarse search: results, and at most min(16, nlist / (8 * queue)) chunk
+    // lists (the exact search's chunk plan)
     const int64_t ks = 64 * (int64_t)mk::queue_regs(std::min(nprobe + 16, mk::kMaxK));
-    const int64_t chunks = std::max<int64_t>(1, ix->nlist / (32 * ks));
+    const int64_t chunks = std::min<int64_t>(16, std::max<int64_t>(1, ix->nlist / (8 * ks)));
     int64_t b = qn * nprobe * (4 + 8) + qn * chunks * ks * 8 + qn * 4;
     b += qn * (int64_t)ix->M * 256 * 4;      // term-3 tables
     b += qn * nprobe * kk * 8;                // per-list partial results

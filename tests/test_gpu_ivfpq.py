@@ -394,6 +394,22 @@ def test_ivfpq_rerank_matches_oracle(api, small_index, k, nprobe, R):
     assert skipped <= 3
 
 
+@pytest.mark.parametrize("k,R", [(10, 100), (10, 1024)])
+def test_ivfpq_rerank_small_batch_kernel_equals_large(api, small_index, k, R):
+    # batches under 4096 queries re-rank with a workgroup per query, larger
+    # ones with a wave per query: the same rows, distances and final sort, so
+    # the same results bit for bit (the short lists do not depend on the
+    # batch: the scan's keys are (distance, id), a total order)
+    say(f"ivfpq rerank small vs large batch kernel k={k} R={R}")
+    ix, xb = small_index["ix"], small_index["xb"]
+    xq = synth.Mixture(100, 32, (11, 0)).sample(5000, (11, 9))
+    Dl, Il = ix.search_rerank(dev(xq), k, 8, R, dev(xb))
+    Ds, Is = ix.search_rerank(dev(xq[:300]), k, 8, R, dev(xb))
+    torch.cuda.synchronize()
+    assert np.array_equal(Is.cpu().numpy(), Il.cpu().numpy()[:300])
+    assert np.array_equal(Ds.cpu().numpy(), Dl.cpu().numpy()[:300])
+
+
 def check_rerank(Dg, Ig, xq, xb, rows, coarse, books, offs, codes, ids, k, nprobe, R):
     """Band rule for re-ranked IVFADC results against the oracle; returns
     (failures, rows skipped as band-ambiguous)."""
