@@ -1511,8 +1511,7 @@ __global__ __launch_bounds__(64 * kMergeWaves) void knn_merge_rerank(
 // 16 rows per wave per step, then wave 0 sorts the (distance, row) keys and
 // writes the first k.  The same rows, distances and final sort as
 // knn_merge_rerank over one chunk of R, so the same results, with a quarter
-// of its gather latency per query: for batches too small to fill the chip
-// with one wave per query.
+// of its gather latency per query.
 template <int KR>
 __global__ __launch_bounds__(64 * kMergeWaves) void knn_rerank_block(
     const uint64_t* __restrict__ keys, int32_t R, const float* __restrict__ xq,

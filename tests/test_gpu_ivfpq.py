@@ -395,12 +395,11 @@ def test_ivfpq_rerank_matches_oracle(api, small_index, k, nprobe, R):
 
 
 @pytest.mark.parametrize("k,R", [(10, 100), (10, 1024)])
-def test_ivfpq_rerank_small_batch_kernel_equals_large(api, small_index, k, R):
-    # batches under 4096 queries re-rank with a workgroup per query, larger
-    # ones with a wave per query: the same rows, distances and final sort, so
-    # the same results bit for bit (the short lists do not depend on the
-    # batch: the scan's keys are (distance, id), a total order)
-    say(f"ivfpq rerank small vs large batch kernel k={k} R={R}")
+def test_ivfpq_rerank_independent_of_batch(api, small_index, k, R):
+    # a query's re-ranked result does not depend on the batch it is searched
+    # in (coarse plan, scan grouping and merge all change with the batch
+    # size; the scan's keys are (distance, id), a total order): bit for bit
+    say(f"ivfpq rerank small vs large batch k={k} R={R}")
     ix, xb = small_index["ix"], small_index["xb"]
     xq = synth.Mixture(100, 32, (11, 0)).sample(5000, (11, 9))
     Dl, Il = ix.search_rerank(dev(xq), k, 8, R, dev(xb))
