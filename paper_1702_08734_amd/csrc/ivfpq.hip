@@ -769,19 +769,24 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
 // (about 8 per CU), so each query's table is staged once for as many lists
 // as possible and fewer partial lists reach the merge; with enough queries
 // every query's lists go to one workgroup (measured on 10^7 x 128, nprobe
-// 128: 11.3 ms per-query against 15.6 ms for groups of 16).
-int32_t scan_group(int64_t total_probes, int32_t nprobe) {
-    const int64_t g = total_probes / 2048;
+// 128: 11.3 ms per-query against 15.6 ms for groups of 16).  Queues of 512+
+// entries aim at 512+ workgroups: each workgroup's merge of its four waves'
+// queues then costs more than the parallelism it buys (5*10^7 x 128,
+// R = 1024, 9 probes per query: 256 queries 1.41 -> 1.15 ms with 4 lists per
+// group, 1024 queries 2.31 -> 1.94 ms with all of a query's lists).
+int32_t scan_group(int64_t total_probes, int32_t nprobe, int32_t k) {
+    const int64_t g = total_probes / (k >= 512 ? 512 : 2048);
     return (int32_t)(g < 1 ? 1 : g > nprobe ? nprobe : g);
 }
 
 // The index's choice of lists per workgroup for nq queries probing up to
 // nprobe lists each: automatic (scan_group), all of a query's lists in one
 // workgroup (the per-query fused scan), or a fixed count.
-int32_t scan_group_of(const mk_ivfpq* ix, int64_t nq, int32_t nprobe, int32_t auto_probes) {
+int32_t scan_group_of(const mk_ivfpq* ix, int64_t nq, int32_t nprobe, int32_t auto_probes,
+                      int32_t k) {
     if (ix->lists_per_group < 0) return nprobe;
     if (ix->lists_per_group > 0) return ix->lists_per_group < nprobe ? ix->lists_per_group : nprobe;
-    return scan_group(nq * (int64_t)auto_probes, nprobe);
+    return scan_group(nq * (int64_t)auto_probes, nprobe, k);
 }
 
 mk_status launch_scan(const float* term3, const float* t1e, const float* cd, const int64_t* ci,
@@ -977,7 +982,7 @@ mk_status scan_fixed(mk_ivfpq* ix, const float* xq, int64_t nq, int32_t nprobe, 
     MK_TRY(cd.alloc(sizeof(float) * nq * nprobe, s));
     MK_TRY(ci.alloc(sizeof(int64_t) * nq * nprobe, s));
     MK_TRY(t3.alloc(sizeof(float) * nq * M * 256, s));
-    const int32_t G = scan_group_of(ix, nq, nprobe, nprobe);
+    const int32_t G = scan_group_of(ix, nq, nprobe, nprobe, kk);
     *ngroups = ceil_div(nprobe, G);
     MK_TRY(part.alloc(sizeof(uint64_t) * nq * *ngroups * kk, s));
     MK_TRY(knn_search(xq, nq, ix->coarse, ix->coarse_norms, ix->nlist, ix->d, nprobe,
@@ -1079,7 +1084,7 @@ mk_status search_learned(mk_ivfpq* ix, const mk_mlp* net, float delta, const flo
     // probe counts and the scan's work plan on the device: the scan grid is
     // sized for tau = cap everywhere and the surplus workgroups return at
     // once, so the search never waits for the host
-    const int32_t G = scan_group_of(ix, nq, cap, cap < 8 ? cap : 8);
+    const int32_t G = scan_group_of(ix, nq, cap, cap < 8 ? cap : 8, kk);
     const int64_t max_items = nq * ceil_div(cap, G);
     hipLaunchKernelGGL(probe_plan_kernel, dim3(1), dim3(1024), 0, s, yhat.as<float>(), nq, delta,
                        cap, G, tau.as<int32_t>(), used, work.as<int64_t>());
