@@ -446,12 +446,20 @@ def learned_probe_section(api, synth, torch, ix, xb, xq, w, recalls):
     progress("learned probe: calibration")
     xcal = torch.from_numpy(mix.sample(10_000, (base, 23))).cuda()
     gcal = api.knn_search(xcal, xb, 1)[1][:, 0].cpu().numpy()
+    def cal_recall(dlt):
+        I = ix.search_learned(net, float(dlt), xcal, k, cap, R, xb)[1].cpu().numpy()
+        return np.mean([gcal[j] in I[j] for j in range(len(gcal))])
+
     delta = None
     for dlt in np.arange(-1.0, 4.01, 0.25):
-        I = ix.search_learned(net, float(dlt), xcal, k, cap, R, xb)[1].cpu().numpy()
-        if np.mean([gcal[j] in I[j] for j in range(len(gcal))]) >= 0.9:
+        if cal_recall(dlt) >= 0.9:
             delta = float(dlt)
             break
+    if delta is not None:  # then in steps of 0.05 below it
+        for dlt in np.arange(delta - 0.2, delta - 0.01, 0.05):
+            if cal_recall(dlt) >= 0.9:
+                delta = round(float(dlt), 2)
+                break
     out = {"train_queries": int(xtr.shape[0]), "epochs": w["learn_epochs"],
            "epoch_loss": [round(v, 4) for v in losses], "train_s": round(t_train, 2),
            "label_mean": round(float(label.float().mean().item()), 2), "R": R, "cap": cap,
