@@ -529,9 +529,11 @@ mk_status mk_ivfpq_search_workspace_bytes(const mk_ivfpq* index, int64_t nq, int
  * batches are in flight at once, each on its own HIP stream with pinned
  * staging buffers, so transfers and kernels of consecutive batches overlap.
  * Each stream also holds a device workspace of
- * mk_ivfpq_search_workspace_bytes for max_batch rows plus a quarter and
- * 64 MiB, allocated at creation, from which its batches' scratch is carved
- * (scratch that does not fit is allocated per search as usual).
+ * mk_ivfpq_search_workspace_bytes for max_batch rows (at most
+ * workspace_budget when that is set) plus a quarter and 64 MiB, allocated at
+ * creation, from which its batches' scratch is carved (scratch that does not
+ * fit, or all of it when the device has no room for the workspace, is
+ * allocated per search as usual).
  * A request's results equal those of searching it alone.
  * ------------------------------------------------------------------------ */
 

@@ -253,8 +253,9 @@ extern "C" mk_status mk_server_create(mk_ivfpq* ix, const mk_server_config* cfg,
     MK_HIP(hipGetDevice(&sv->device));
     sv->slots.resize(cfg->nstreams);
     const size_t B = (size_t)cfg->max_batch;
-    // per-slot search workspace: the estimate for a full batch plus a margin
-    // for what it leaves out (scratch that does not fit is allocated as usual)
+    // per-slot search workspace: the estimate for a full batch (at most the
+    // per-batch budget, when one is set) plus a margin for what it leaves
+    // out; scratch that does not fit is allocated per search as usual
     size_t ws = 0;
     {
         mk_status st = mk_ivfpq_search_workspace_bytes(ix, cfg->max_batch, cfg->k,
@@ -262,6 +263,8 @@ extern "C" mk_status mk_server_create(mk_ivfpq* ix, const mk_server_config* cfg,
                                                        &ws);
         if (st != MK_OK) return st;
     }
+    if (cfg->workspace_budget > 0 && ws > (size_t)cfg->workspace_budget)
+        ws = (size_t)cfg->workspace_budget;
     ws += ws / 4 + ((size_t)64 << 20);
     hipError_t e = hipSuccess;
     for (Slot& sl : sv->slots) {
@@ -273,8 +276,18 @@ extern "C" mk_status mk_server_create(mk_ivfpq* ix, const mk_server_config* cfg,
         if (e == hipSuccess) e = hipMalloc(&sl.d_q, sizeof(float) * B * d);
         if (e == hipSuccess) e = hipMalloc(&sl.d_D, sizeof(float) * B * cfg->k);
         if (e == hipSuccess) e = hipMalloc(&sl.d_I, sizeof(int64_t) * B * cfg->k);
-        if (e == hipSuccess) e = hipMalloc(&sl.d_ws, ws);
-        if (e == hipSuccess) sl.ws_bytes = ws;
+        if (e == hipSuccess) {
+            // without room for the workspace the slot allocates per search
+            const hipError_t ew = hipMalloc(&sl.d_ws, ws);
+            if (ew == hipSuccess) {
+                sl.ws_bytes = ws;
+            } else if (ew == hipErrorOutOfMemory) {
+                (void)hipGetLastError();
+                sl.d_ws = nullptr;
+            } else {
+                e = ew;
+            }
+        }
     }
     if (e != hipSuccess) {
         mk::release(sv.get());
