@@ -496,9 +496,9 @@ int32_t mk_ivfpq_dim(const mk_ivfpq* index);
  *                  Entries must satisfy |2 term3| < 65504.
  *   lists_per_group  probed lists of one query scanned by one workgroup:
  *                  0 (default) chosen from the launch size: as many
- *                  lists per workgroup as keep 2048 or more workgroups
+ *                  lists per workgroup as keep 1024 or more workgroups
  *                  (512 or more for short lists of k or R >= 512; all of
- *                  a query's lists from about 2048 / 512 queries on),
+ *                  a query's lists from about 1024 / 512 queries on),
  *                  -1 all of a query's lists (the per-query fused scan of
  *                  Section 5.3), or a count 1..1024.
  * Results do not depend on lists_per_group (candidates are keyed by

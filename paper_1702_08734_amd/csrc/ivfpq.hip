@@ -765,17 +765,20 @@ __global__ __launch_bounds__(64 * kScanWaves) void ivf_scan(
     }
 }
 
-// Lists per workgroup: as many as keep the launch at 2048+ workgroups
-// (about 8 per CU), so each query's table is staged once for as many lists
+// Lists per workgroup: as many as keep the launch at 1024+ workgroups
+// (about 4 per CU), so each query's table is staged once for as many lists
 // as possible and fewer partial lists reach the merge; with enough queries
-// every query's lists go to one workgroup (measured on 10^7 x 128, nprobe
-// 128: 11.3 ms per-query against 15.6 ms for groups of 16).  Queues of 512+
-// entries aim at 512+ workgroups: each workgroup's merge of its four waves'
-// queues then costs more than the parallelism it buys (5*10^7 x 128,
+// every query's lists go to one workgroup (10^7 x 128, 4096 lists, k = 100:
+// nprobe 128 and 10^4 queries 11.3 ms per-query against 15.6 ms for groups
+// of 16; 1024 queries, nprobe 8 / 64 / 128, 0.47 / 1.41 / 2.65 ms at 2048+
+// workgroups against 0.42 / 1.29 / 2.49 ms; 256 queries, nprobe 64 with
+// R = 256 0.90 -> 0.85 ms, and larger groups than that slower).  Queues of
+// 512+ entries aim at 512+ workgroups: each workgroup's merge of its four
+// waves' queues costs more than the parallelism it buys (5*10^7 x 128,
 // R = 1024, 9 probes per query: 256 queries 1.41 -> 1.15 ms with 4 lists per
 // group, 1024 queries 2.31 -> 1.94 ms with all of a query's lists).
 int32_t scan_group(int64_t total_probes, int32_t nprobe, int32_t k) {
-    const int64_t g = total_probes / (k >= 512 ? 512 : 2048);
+    const int64_t g = total_probes / (k >= 512 ? 512 : 1024);
     return (int32_t)(g < 1 ? 1 : g > nprobe ? nprobe : g);
 }
 
