@@ -207,6 +207,12 @@ def pq_decode(codes, codebooks):
     return np.concatenate(parts, axis=1)
 
 
+def rotate_rows(x, rot):
+    """Linear pre-processing of the input vectors (an OPQ rotation, Sections
+    1 and 6.4): out[i][j] = sum_t rot[j][t] x[i][t], float64."""
+    return _f64(x) @ _f64(rot).T
+
+
 def ivfpq_train(xt, nlist: int, M: int, niter: int, coarse_init_rows, pq_init_rows):
     """Train q1 (k-means, nlist centroids) then q2 (M independent 256-centroid
     k-means on contiguous residual sub-vectors), Section 2 "The quantizers"

@@ -536,3 +536,20 @@ def test_ivfpq_graph_drops_only_the_node():
         keep = Ia[j] != n
         np.testing.assert_array_equal(I[j], Ia[j][keep][:k])
         np.testing.assert_array_equal(D[j], Da[j][keep][:k])
+
+
+def test_rotate_rows_permutation_and_orthogonal():
+    # a permutation matrix moves columns exactly; an orthogonal matrix keeps
+    # every row's norm and is undone by its transpose; a transposed operand
+    # or a wrong index fails one of these
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((37, 12))
+    perm = rng.permutation(12)
+    P = np.eye(12)[perm]                      # row j selects column perm[j]
+    assert np.array_equal(oracle.rotate_rows(x, P), x[:, perm])
+    Q, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    y = oracle.rotate_rows(x, Q)
+    assert np.allclose(np.linalg.norm(y, axis=1), np.linalg.norm(x, axis=1), rtol=1e-12)
+    assert np.allclose(oracle.rotate_rows(y, Q.T), x, atol=1e-12)
+    # a rectangular projection (dout < d) keeps the first dout coordinates
+    assert np.array_equal(oracle.rotate_rows(x, np.eye(12)[:5]), x[:, :5])
