@@ -64,6 +64,22 @@ int32_t mk_version(void);
 mk_status mk_norms(const float* x, int64_t n, int32_t d, float* out, mk_stream_t stream);
 
 /*
+ * Linear pre-processing of rows, such as an OPQ rotation applied to database
+ * and query vectors before indexing and search (Section 1: OPQ is a linear
+ * transform of the inputs usable as pre-processing; Section 6.4 reduces
+ * Deep1B with it): out[i][j] = sum_t rot[j][t] * x[i][t].
+ *   x   [n, d] float32     rot [dout, d] float32 (a rotation: dout = d; a
+ *                          projection: dout < d)     out [n, dout] float32
+ * Device pointers, row-major; out must not overlap x (MK_ERR_INVALID_ARG).
+ * FP32 matrix-core products, one fixed summation order per element, so the
+ * result is deterministic; it errs from the exact product by at most about
+ * d * 2^-24 * sum_t |rot[j][t] x[i][t]|.  Learning the rotation is not part
+ * of the library.
+ */
+mk_status mk_rotate_rows(const float* x, int64_t n, int32_t d, const float* rot, int32_t dout,
+                         float* out, mk_stream_t stream);
+
+/*
  * Row-wise k-selection (Section 2 problem statement; Section 4.2 WarpSelect,
  * rebuilt for 64-lane wavefronts): for each row of a resident matrix return
  * the k lowest values (largest = 0) or the k highest (largest != 0) with

@@ -38,6 +38,7 @@ _SIGS = {
     "mk_last_error": [],
     "mk_version": [],
     "mk_norms": [_vp, _i64, _i32, _vp, _vp],
+    "mk_rotate_rows": [_vp, _i64, _i32, _vp, _i32, _vp, _vp],
     "mk_kselect": [_vp, _i64, _i64, _i32, _i32, _vp, _vp, _vp],
     "mk_knn_search": [_vp, _i64, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
     "mk_knn_search_noalloc": [_vp, _i64, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
@@ -151,6 +152,18 @@ def norms(x: torch.Tensor) -> torch.Tensor:
     _dev(x, torch.float32, "x")
     out = _out((x.shape[0],), torch.float32, x)
     _call("mk_norms", _ptr(x), x.shape[0], x.shape[1], _ptr(out), _stream())
+    return out
+
+
+def rotate_rows(x: torch.Tensor, rot: torch.Tensor) -> torch.Tensor:
+    """out[i][j] = sum_t rot[j][t] x[i][t] (an OPQ rotation or projection)."""
+    _dev(x, torch.float32, "x")
+    _dev(rot, torch.float32, "rot")
+    if rot.dim() != 2 or rot.shape[1] != x.shape[1]:
+        raise ValueError("rot must be [dout, d] with d = x.shape[1]")
+    out = _out((x.shape[0], rot.shape[0]), torch.float32, x)
+    _call("mk_rotate_rows", _ptr(x), x.shape[0], x.shape[1], _ptr(rot), rot.shape[0], _ptr(out),
+          _stream())
     return out
 
 
