@@ -170,6 +170,29 @@ def small_exact_section(api, synth, torch):
             "TFLOP/s": round(2 * 500 * 50_000 * 64 / dt / 1e12, 2)}
 
 
+def rotate_section(api, synth, torch):
+    """Row rotation (OPQ-style pre-processing): 10,000,000 x 128 FP32 rows
+    times a 128 x 128 orthogonal matrix; 2 n d^2 flop against 2 n d 4 bytes,
+    so the FP32 matrix cores bound it (0.34 TFLOP: 2.1 ms at 157.3 TFLOP/s;
+    10.2 GB: 1.3 ms at 8 TB/s)."""
+    import numpy as np
+    n, d = 10_000_000, 128
+    g = torch.Generator(device="cuda")
+    g.manual_seed(41)
+    x = torch.randn((n, d), generator=g, device="cuda", dtype=torch.float32)
+    q, _ = np.linalg.qr(np.random.default_rng(41).standard_normal((d, d)))
+    rot = torch.from_numpy(q.astype(np.float32)).cuda()
+    dt, dmin = _timed(torch, lambda: api.rotate_rows(x, rot))
+    flop = 2.0 * n * d * d
+    tf = flop / dt / 1e12
+    del x
+    torch.cuda.empty_cache()
+    return {"workload": "10,000,000 x 128 float32 rows times a 128 x 128 rotation",
+            "ms": round(dt * 1e3, 3), "ms_min": round(dmin * 1e3, 3), "TFLOP/s": round(tf, 2),
+            "frac_fp32_mfma_peak": round(tf / FP32_MFMA_PEAK_TFLOPS, 4),
+            "GB/s": round(2 * n * d * 4 / dt / 1e9, 1)}
+
+
 def lowp_section(api, synth, torch, oracle_queries=32):
     """BF16 / FP8-E4M3 brute force on the matrix cores with an exact FP32
     re-rank of the R = 4k best against FP32 brute force: 20,000,000 x 96
@@ -686,7 +709,8 @@ def main() -> int:
     ap.add_argument("--skip-large", action="store_true",
                     help="leave out the 50,000,000-vector IVFADC section")
     ap.add_argument("--section", default=None,
-                    help="only this extra section (small_exact, kselect, ivfpq, lowp, ivf_large), "
+                    help="only this extra section (small_exact, kselect, ivfpq, lowp, ivf_large, host_db, "
+                         "rotate), "
                          "for profiling runs")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -714,7 +738,7 @@ def main() -> int:
     if args.section:
         fns = {"small_exact": small_exact_section, "kselect": kselect_section,
                "ivfpq": ivfpq_section, "lowp": lowp_section, "ivf_large": ivf_large_run,
-               "host_db": host_db_section}
+               "host_db": host_db_section, "rotate": rotate_section}
         print(json.dumps({args.section: fns[args.section](api, synth, torch)}), flush=True)
         return 0
 
@@ -804,7 +828,7 @@ def main() -> int:
     if not args.skip_extra:
         sections = [("small_exact", small_exact_section), ("kselect", kselect_section),
                     ("ivfpq", ivfpq_section), ("lowp", lowp_section),
-                    ("host_db", host_db_section)]
+                    ("host_db", host_db_section), ("rotate", rotate_section)]
         if not args.skip_large:
             sections.append(("ivf_large", ivf_large_run))
         for name, fn in sections:
