@@ -408,31 +408,6 @@ mk_status mlp_forward_dev(const mk_mlp* net, const float* F, int64_t n, float* y
 
 }  // namespace mk
 
-// Linear pre-processing of rows (an OPQ rotation, Sections 1 and 6.4): the
-// FP32 MFMA product of the network's layers, launched over row blocks of at
-// most 65535 x 64 rows (the grid's y extent).
-extern "C" mk_status mk_rotate_rows(const float* x, int64_t n, int32_t d, const float* rot,
-                                    int32_t dout, float* out, mk_stream_t stream) {
-    MK_REQUIRE(n >= 0 && d >= 1 && dout >= 1, MK_ERR_INVALID_ARG, "need n >= 0, d >= 1, dout >= 1");
-    if (n == 0) return MK_OK;
-    MK_REQUIRE(x && rot && out, MK_ERR_INVALID_ARG, "null pointer");
-    const char* xe = reinterpret_cast<const char*>(x + n * (int64_t)d);
-    const char* oe = reinterpret_cast<const char*>(out + n * (int64_t)dout);
-    MK_REQUIRE(xe <= reinterpret_cast<const char*>(out) || oe <= reinterpret_cast<const char*>(x),
-               MK_ERR_INVALID_ARG, "out must not overlap x");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    constexpr int64_t kRowsPerLaunch = (int64_t)65535 * 64;
-    for (int64_t r0 = 0; r0 < n; r0 += kRowsPerLaunch) {
-        const int64_t m = n - r0 < kRowsPerLaunch ? n - r0 : kRowsPerLaunch;
-        // out[i][j] = sum_t x[i][t] * rot[j][t]: B[t][j] = rot[j][t]
-        mk::GemmArgs g = mk::gemm_args(x + r0 * d, d, 1, rot, 1, d, out + r0 * dout, dout, m, dout, d);
-        const dim3 grid((unsigned)mk::ceil_div(dout, 64), (unsigned)mk::ceil_div(m, 64));
-        hipLaunchKernelGGL(mk::mlp_gemm<false>, grid, dim3(256), 0, s, g);
-        MK_LAUNCHED();
-    }
-    return MK_OK;
-}
-
 // ---------------------------------------------------------------- C ABI
 extern "C" mk_status mk_mlp_create(int32_t din, int32_t hidden, mk_precision prec,
                                    mk_mlp** out) {
